@@ -1,0 +1,167 @@
+/*
+ * hifde.h -- C ABI of the MI355X (gfx950) implementation of the hierarchical
+ * interpolative factorization for elliptic PDEs (HIF-DE; K. L. Ho and L. Ying,
+ * "Hierarchical Interpolative Factorization for Elliptic Operators:
+ * Differential Equations").
+ *
+ * Problem (Section 1, Eq. (1)-(2); Sections 3.1-3.2): -div(a grad u) + b u = f
+ * on the unit square (dim = 2) or cube (dim = 3) with homogeneous Dirichlet
+ * data, discretized by the five-/seven-point stencil with a on the staggered
+ * links and b at the nodes.  There are n unknowns per side, N = n^dim, grid
+ * spacing h = 1/(n+1), lexicographic order with x0 fastest.  The library
+ * factors the sparse matrix A approximately as the generalized LDL form of
+ * Section 4.1 (A ~= F = V_0^-T ... V_{L-1/2}^-T D V_{L-1/2}^-1 ... V_0^-1,
+ * Algorithm 4.1) and applies F^-1, directly or as the preconditioner of
+ * conjugate gradients (Section 5).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns a hifde_status (0 on success, < 0 on error); the
+ *     message of the last failing call on the calling thread is returned by
+ *     hifde_last_error().  No C++ exception crosses this interface.
+ *   - Device pointers are HIP device pointers on the current device; host
+ *     pointers are plain host memory.  Each argument says which it is.
+ *   - hip_stream is a hipStream_t passed as void*; NULL means the default
+ *     stream.  All device work of a call is ordered on that stream; calls that
+ *     return results to host memory synchronize it.
+ *   - Handles own every buffer they allocate and are released by the matching
+ *     *_free call.  Inputs are copied during the call and stay owned by the
+ *     caller.  A handle must not be used from two threads at once; distinct
+ *     handles are independent.
+ */
+#ifndef HIFDE_H
+#define HIFDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hifde_tree_s* hifde_tree_t;
+typedef struct hifde_factor_s* hifde_factor_t;
+
+typedef enum {
+  HIFDE_OK = 0,
+  HIFDE_EINVAL = -1,   /* invalid argument                                  */
+  HIFDE_ENOMEM = -2,   /* device or host allocation failed                  */
+  HIFDE_EDEVICE = -3,  /* a HIP runtime call failed                         */
+  HIFDE_ENOTSPD = -4,  /* a diagonal block had a non-positive pivot         */
+  HIFDE_ENOCONV = -5,  /* PCG did not reach the tolerance within maxit      */
+  HIFDE_ESTATE = -6    /* handle in the wrong state for this call           */
+} hifde_status;
+
+typedef enum {
+  HIFDE_FP64 = 0,      /* every step in double precision                    */
+  HIFDE_MIXED = 1      /* cell/group steps and F^-1 in float; the top block
+                          factorization, residuals and PCG in double         */
+} hifde_precision;
+
+enum {
+  HIFDE_DEBUG_DETERMINISM = 4u  /* factor every level twice, compare bitwise */
+};
+
+/* Maximum number of tree levels reported by hifde_stats. */
+#define HIFDE_MAX_LEVELS 24
+
+typedef struct {
+  int64_t N;                        /* number of unknowns                     */
+  int32_t dim, levels;              /* dimension and tree depth L             */
+  int64_t top_size;                 /* |s_L|, the unknowns left at level L    */
+  int64_t factor_bytes;             /* m_f: device bytes of the stored factor */
+  double factor_flops;              /* algorithmic flops of the factorization */
+  double factor_ms;                 /* wall time of the last hifde_factor     */
+  double solve_bytes;               /* algorithmic bytes of one F^-1 sweep    */
+  int64_t cells[HIFDE_MAX_LEVELS];  /* cells eliminated at level l            */
+  int64_t groups[HIFDE_MAX_LEVELS]; /* groups at level l+1/2                  */
+  int64_t skel_in[HIFDE_MAX_LEVELS];  /* unknowns entering level l+1/2 groups  */
+  int64_t skel_out[HIFDE_MAX_LEVELS]; /* skeletons kept at level l+1/2         */
+  int32_t max_front[HIFDE_MAX_LEVELS];/* largest |p|+|c^N| of a level-l cell   */
+} hifde_stats_t;
+
+/* Index sets of one (fractional) level, for comparison with other
+ * implementations.  level2 = 2l selects the cells of level l (lists 0 = p,
+ * the eliminated unknowns, and 1 = c^N, the front); level2 = 2l+1 selects the
+ * groups of level l+1/2 (lists 0 = c, 1 = c^N, 2 = skeletons, 3 = redundant);
+ * level2 = 2L selects the top block (one entry, list 0 = s_L).  Every list is
+ * sorted ascending and holds global unknown indices. */
+typedef struct {
+  int64_t count;      /* number of cells or groups                           */
+  int64_t total[4];   /* total length of each list over all entries          */
+  int64_t* ids;       /* [count] cell or group keys (host, caller-owned)     */
+  int64_t* offs[4];   /* [count+1] start of each entry in lists[i]           */
+  int32_t* lists[4];  /* concatenated lists (host, caller-owned)             */
+} hifde_sets_t;
+
+/* Build the uniform tree of Sections 3.1-3.2 and 4.1-4.2: n unknowns per side,
+ * leaf boxes of `leaf` unknowns per side, L = log2(n/leaf) levels.  The first
+ * `skip_levels` fractional levels are not skeletonized (Section 5).
+ * Host-only; no device work.
+ * EINVAL: dim not 2 or 3, leaf < 2, n/leaf not a power of two >= 2,
+ * skip_levels < 0, N >= 2^31. */
+int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels,
+                     hifde_tree_t* out);
+
+/* Factor A (Algorithm 4.1).  a[k] (k < dim) are DEVICE pointers to double
+ * arrays of the link coefficients along axis k: n+1 links along axis k and n
+ * along the others, x0 fastest (link j along axis k joins x_k = j-1 and
+ * x_k = j).  b is a DEVICE pointer to N doubles or NULL (b = 0).  eps is the
+ * relative ID tolerance of Section 2.2; eps = 0 disables skeletonization
+ * (the multifrontal method, Algorithm 3.1).  The returned factor keeps no
+ * reference to a or b.
+ * EINVAL: eps outside [0, 1), NULL a[k], non-positive or non-finite a
+ * (checked on the device), non-finite b.  ENOTSPD: a pivot of a diagonal
+ * block was not positive; hifde_last_error() names the level and block. */
+int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b,
+                 double eps, hifde_precision prec, uint32_t flags,
+                 void* hip_stream, hifde_factor_t* out);
+
+/* u = F^-1 f for nrhs right-hand sides (the factored application of
+ * Section 4.1).  f and u are DEVICE pointers to N x nrhs column-major double
+ * arrays with leading dimensions ldf, ldu >= N; f may equal u.
+ * EINVAL: nrhs < 1, ld < N, NULL pointers. */
+int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
+                double* u, int64_t ldu, void* hip_stream);
+
+/* Solve A u = f by conjugate gradients preconditioned with F^-1 (Section 5),
+ * from u = 0, in double precision, one independent iteration per column,
+ * until ||f - A u|| <= tol ||f|| (recursive residual) or maxit iterations.
+ * The mixed-precision factor uses the flexible (Polak-Ribiere) update.
+ * f, u: DEVICE, N x nrhs column-major.  iters[nrhs], relres[nrhs]: HOST,
+ * filled with the iteration count and the true relative residual
+ * ||f - A u|| / ||f|| of each column.
+ * ENOCONV: some column missed tol; iters, relres and u hold the last iterate. */
+int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
+              double* u, int64_t ldu, double tol, int maxit, int* iters,
+              double* relres, void* hip_stream);
+
+/* y = A x with the assembled stencil (the operator PCG uses).  DEVICE,
+ * N x nrhs column-major. */
+int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
+                 double* y, int64_t ldy, void* hip_stream);
+
+/* Statistics of a factor (HOST out). */
+int hifde_stats(hifde_factor_t F, hifde_stats_t* out);
+
+/* Index sets of one level (see hifde_sets_t).  Call once with every pointer
+ * in *out NULL to obtain count and totals, then again with caller-allocated
+ * host buffers of those sizes.  Works on factors and on replayed plans. */
+int hifde_export_sets(hifde_factor_t F, int level2, hifde_sets_t* out);
+
+/* Host-only replay of the tree and index-set construction: the skeletons of
+ * every level l+1/2 are taken from redundant_level (HOST, N int32: 2l+1 if
+ * the unknown is redundant at level l+1/2, any other value otherwise)
+ * instead of being computed.  The result supports hifde_export_sets and
+ * hifde_stats only.  Needs no GPU. */
+int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level,
+                      hifde_factor_t* out);
+
+void hifde_tree_free(hifde_tree_t tree);
+void hifde_factor_free(hifde_factor_t F);
+const char* hifde_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIFDE_H */

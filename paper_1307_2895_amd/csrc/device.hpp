@@ -1,0 +1,55 @@
+// Descriptors shared by the host orchestration and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hifde {
+
+// A symmetric block read by extend-add: column-major, only its lower
+// triangle is valid.  rowmap/colmap index the level's map array and give the
+// destination row/column of every source index (-1 drops it).
+struct SrcDev {
+  const void* ptr;
+  int64_t ld;
+  int32_t dim;
+  int32_t pad;
+  int64_t rowmap;
+  int64_t colmap;
+};
+
+// One loose stencil entry: destination (i, j) and the stencil value ref
+// (ref < N: diagonal of unknown ref; else offd[ref - N]).
+struct TripDev {
+  int32_t i, j;
+  int64_t ref;
+};
+
+// A dense symmetric matrix (column-major, ld = s) in a pool, of which the
+// leading p pivots are eliminated by the partial LDL^T.
+struct FrontDev {
+  int64_t off;
+  int32_t s;
+  int32_t p;
+  int32_t src_begin, src_end;
+  int64_t trip_begin, trip_end;
+  int64_t idx;      // offset of the front's [p; q] unknown list (solve)
+  int32_t color;    // 0/1 checkerboard parity (solve, upward sweep)
+  int32_t pad;
+};
+
+// A skeletonization group.
+struct GroupDev {
+  int64_t gw_off;    // [c^N; c] x c workspace (ld = nn + nc)
+  int64_t base_off;  // base block E_G (nc x nc, lower)
+  int64_t fg_off;    // frontal matrix [r; s] x [r; s] (nc x nc)
+  int64_t t_off;     // interpolation matrix T (k x r, ld = k)
+  int32_t nn, nc;
+  int32_t src_begin, src_end;    // cell update blocks feeding the workspace
+  int64_t trip_begin, trip_end;  // loose links into the workspace
+  int64_t idx;       // offset of the group's unknown list [r; s] (solve)
+  int32_t k;         // skeleton count (filled after the ID)
+  int32_t skel;      // 1 if skeletonized
+};
+
+}  // namespace hifde

@@ -1,0 +1,888 @@
+// HIF-DE on gfx950: C ABI, factorization driver (Algorithm 4.1), F^-1
+// application and preconditioned conjugate gradients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hifde.h"
+#include "device.hpp"
+#include "planner.hpp"
+
+#include "kernels_factor.inc"
+#include "kernels_solve.inc"
+
+namespace hifde {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(x)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      throw ::hifde::Error(e_ == hipErrorOutOfMemory ? HIFDE_ENOMEM : HIFDE_EDEVICE,  \
+                           std::string(#x) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+// Owning device allocation.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    HIP_CHECK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+  template <class T> void upload(const std::vector<T>& v, hipStream_t st) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(p, v.data(), bytes, hipMemcpyHostToDevice, st));
+  }
+};
+
+struct CellLevelDev {
+  DevMem pool;                  // frontal matrices
+  std::vector<FrontDev> fh;
+  DevMem fronts, srcs, maps, trips, idx, info;
+  int64_t elems = 0;
+  int pmax = 0, smax = 0, ncell = 0;
+  bool dbl = false;             // pool holds doubles (top block)
+};
+
+struct GroupLevelDev {
+  std::vector<GroupDev> gh;
+  DevMem groups, bfronts, fgfronts, maps, bsrcs, btrips, gsrcs, gtrips;
+  DevMem gw, base, fg, tpool, kout, perm, gsel, idx, info;
+  int64_t perm_stride = 0;
+  int nskel = 0, ngroup = 0;
+  std::vector<int32_t> gsel_h;
+};
+
+}  // namespace hifde
+
+using namespace hifde;
+
+struct hifde_tree_s {
+  Geom g;
+};
+
+struct hifde_factor_s {
+  Geom g;
+  hifde_precision prec = HIFDE_FP64;
+  double eps = 0.0;
+  bool plan_only = false;
+  std::unique_ptr<Planner> planner;
+  std::vector<CellLevelDev> cl;   // L + 1 entries (last = top)
+  std::vector<GroupLevelDev> gl;  // L entries
+  DevMem diag, offd;
+  hifde_stats_t stats{};
+  // solver scratch
+  DevMem X;
+  int64_t X_rhs = 0;
+  DevMem pcg;
+  int64_t pcg_rhs = 0;
+};
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class Fn> static int guarded(Fn&& fn) {
+  try {
+    fn();
+    return HIFDE_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HIFDE_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HIFDE_EINVAL, e.what());
+  }
+}
+
+namespace hifde {
+
+static inline unsigned nblk(int64_t n, int t = kThreads) { return unsigned((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Source resolution: device address and leading dimension of a planned block.
+// ---------------------------------------------------------------------------
+static SrcDev resolve(const hifde_factor_s& F, const Source& s, size_t esz) {
+  SrcDev d{};
+  d.dim = s.dim;
+  d.rowmap = s.rowmap;
+  d.colmap = s.colmap;
+  if (s.kind == SRC_CELL_U) {
+    const CellLevelDev& L = F.cl.at(s.level);
+    const FrontDev& f = L.fh.at(s.index);
+    const int64_t off = f.off + f.p + int64_t(f.p) * f.s;
+    d.ptr = static_cast<const char*>(L.pool.p) + off * int64_t(esz);
+    d.ld = f.s;
+  } else {
+    const GroupLevelDev& G = F.gl.at(s.level);
+    const GroupDev& g = G.gh.at(s.index);
+    if (g.skel) {
+      const int r = g.nc - g.k;
+      const int64_t off = g.fg_off + r + int64_t(r) * g.nc;
+      d.ptr = static_cast<const char*>(G.fg.p) + off * int64_t(esz);
+    } else {
+      d.ptr = static_cast<const char*>(G.base.p) + g.base_off * int64_t(esz);
+    }
+    d.ld = g.nc;
+  }
+  return d;
+}
+
+static void append_trips(std::vector<TripDev>& out, const std::vector<Trip>& in) {
+  for (const Trip& t : in) out.push_back({t.i, t.j, t.ref});
+}
+
+// Batched partial LDL^T of a set of fronts already in `pool`.
+template <typename T>
+static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
+                        int* info_d, hipStream_t st) {
+  if (fh.empty()) return;
+  int pmax = 0;
+  for (const auto& f : fh) pmax = std::max(pmax, f.p);
+  const unsigned nf = unsigned(fh.size());
+  for (int j0 = 0; j0 < pmax; j0 += kNB) {
+    int64_t maxt = 0;
+    for (const auto& f : fh) {
+      if (j0 >= f.p) continue;
+      int r0 = std::min(j0 + kNB, f.p);
+      int64_t nt = f.s - r0;
+      if (nt <= 0) continue;
+      int64_t T_ = (nt + kTB - 1) / kTB;
+      maxt = std::max(maxt, T_ * (T_ + 1) / 2);
+    }
+    hipLaunchKernelGGL(k_ldl_panel<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, j0, info_d);
+    if (maxt > 0) {
+      if (maxt > 65535) throw Error(HIFDE_EINVAL, "front too large for the trailing-update grid");
+      hipLaunchKernelGGL(k_ldl_update<T>, dim3(nf, unsigned(maxt)), dim3(kThreads), 0, st, pool,
+                         fronts_d, j0);
+    }
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Cells of level l: plan, assemble, factor.
+// ---------------------------------------------------------------------------
+template <typename T, typename TS>
+static void cells_level(hifde_factor_s& F, int l, hipStream_t st) {
+  Planner& P = *F.planner;
+  P.plan_cells(l);
+  const Level& lev = P.levels()[l];
+  CellLevelDev& D = F.cl[l];
+  D.dbl = sizeof(T) == 8;
+  D.fh.clear();
+  std::vector<SrcDev> srcs;
+  std::vector<TripDev> trips;
+  std::vector<int32_t> idx;
+  int64_t off = 0;
+  D.pmax = D.smax = 0;
+  for (const Cell& c : lev.cells) {
+    FrontDev f{};
+    f.off = off;
+    f.p = int32_t(c.p.size());
+    f.s = int32_t(c.p.size() + c.q.size());
+    f.src_begin = int32_t(srcs.size());
+    for (const Source& s : c.src) srcs.push_back(resolve(F, s, sizeof(TS)));
+    f.src_end = int32_t(srcs.size());
+    f.trip_begin = int64_t(trips.size());
+    append_trips(trips, c.trips);
+    f.trip_end = int64_t(trips.size());
+    f.idx = int64_t(idx.size());
+    idx.insert(idx.end(), c.p.begin(), c.p.end());
+    idx.insert(idx.end(), c.q.begin(), c.q.end());
+    f.color = c.color;
+    off += int64_t(f.s) * f.s;
+    D.pmax = std::max(D.pmax, f.p);
+    D.smax = std::max(D.smax, f.s);
+    D.fh.push_back(f);
+  }
+  D.elems = off;
+  D.ncell = int(D.fh.size());
+  if (F.plan_only) return;
+  D.pool.alloc(size_t(off) * sizeof(T));
+  HIP_CHECK(hipMemsetAsync(D.pool.p, 0, D.pool.bytes, st));
+  D.fronts.upload(D.fh, st);
+  D.srcs.upload(srcs, st);
+  D.maps.upload(lev.maps, st);
+  D.trips.upload(trips, st);
+  D.idx.upload(idx, st);
+  D.info.alloc(sizeof(int) * std::max<size_t>(1, D.fh.size()));
+  HIP_CHECK(hipMemsetAsync(D.info.p, 0, D.info.bytes, st));
+  hipLaunchKernelGGL((k_assemble<T, TS>), dim3(D.ncell), dim3(kThreads), 0, st, D.pool.as<T>(),
+                     D.fronts.as<FrontDev>(), D.srcs.as<SrcDev>(), D.maps.as<int32_t>(),
+                     D.trips.as<TripDev>(), F.diag.as<double>(), F.offd.as<double>(), F.g.N);
+  HIP_CHECK(hipGetLastError());
+  batched_ldl<T>(D.pool.as<T>(), D.fh, D.fronts.as<FrontDev>(), D.info.as<int>(), st);
+}
+
+static void check_info(const DevMem& info, size_t n, const char* what, int l, hipStream_t st) {
+  if (n == 0) return;
+  std::vector<int> h(n);
+  HIP_CHECK(hipMemcpyAsync(h.data(), info.p, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (size_t i = 0; i < n; ++i)
+    if (h[i] != 0) {
+      char buf[200];
+      snprintf(buf, sizeof buf, "non-positive pivot in %s %zu of level %d (panel at %d)", what, i, l,
+               h[i] - 1);
+      throw Error(HIFDE_ENOTSPD, buf);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Groups of level l+1/2: plan, base blocks, ID, skeleton fronts.
+// ---------------------------------------------------------------------------
+template <typename T>
+static void groups_level(hifde_factor_s& F, int l, hipStream_t st) {
+  Planner& P = *F.planner;
+  const bool skel = F.eps > 0.0 && l >= F.g.skip;
+  P.plan_groups(l, skel);
+  Level& lev = P.levels()[l];
+  GroupLevelDev& G = F.gl[l];
+  G.gh.clear();
+  G.ngroup = int(lev.groups.size());
+  std::vector<FrontDev> bf;
+  std::vector<SrcDev> bsrcs, gsrcs;
+  std::vector<TripDev> btrips, gtrips;
+  int64_t base_off = 0, gw_off = 0, t_off = 0;
+  int ncmax = 0;
+  for (const Group& g : lev.groups) {
+    GroupDev d{};
+    d.nc = int32_t(g.c.size());
+    d.nn = int32_t(g.cN.size());
+    d.base_off = base_off;
+    d.gw_off = gw_off;
+    d.t_off = t_off;
+    FrontDev f{};
+    f.off = base_off;
+    f.s = d.nc;
+    f.p = 0;
+    f.src_begin = int32_t(bsrcs.size());
+    for (const Source& s : g.bsrc) bsrcs.push_back(resolve(F, s, sizeof(T)));
+    f.src_end = int32_t(bsrcs.size());
+    f.trip_begin = int64_t(btrips.size());
+    append_trips(btrips, g.btrips);
+    f.trip_end = int64_t(btrips.size());
+    bf.push_back(f);
+    d.src_begin = int32_t(gsrcs.size());
+    for (const Source& s : g.gsrc) gsrcs.push_back(resolve(F, s, sizeof(T)));
+    d.src_end = int32_t(gsrcs.size());
+    d.trip_begin = int64_t(gtrips.size());
+    append_trips(gtrips, g.gtrips);
+    d.trip_end = int64_t(gtrips.size());
+    base_off += int64_t(d.nc) * d.nc;
+    if (skel) {
+      gw_off += (int64_t(d.nn) + d.nc) * d.nc;
+      t_off += int64_t(d.nc) * d.nc / 4 + 1;  // k (n-k) <= n^2/4
+    }
+    ncmax = std::max(ncmax, int(d.nc));
+    G.gh.push_back(d);
+  }
+  if (F.plan_only) return;
+  G.base.alloc(size_t(base_off) * sizeof(T));
+  HIP_CHECK(hipMemsetAsync(G.base.p, 0, G.base.bytes, st));
+  G.bfronts.upload(bf, st);
+  G.maps.upload(lev.maps, st);
+  G.bsrcs.upload(bsrcs, st);
+  G.btrips.upload(btrips, st);
+  if (G.ngroup > 0) {
+    hipLaunchKernelGGL((k_assemble<T, T>), dim3(G.ngroup), dim3(kThreads), 0, st, G.base.as<T>(),
+                       G.bfronts.as<FrontDev>(), G.bsrcs.as<SrcDev>(), G.maps.as<int32_t>(),
+                       G.btrips.as<TripDev>(), F.diag.as<double>(), F.offd.as<double>(), F.g.N);
+    HIP_CHECK(hipGetLastError());
+  }
+  if (!skel || G.ngroup == 0) {
+    for (size_t gi = 0; gi < lev.groups.size(); ++gi) P.set_skeleton(l, int(gi), G.gh[gi].nc, nullptr);
+    P.finish_groups(l);
+    G.nskel = 0;
+    G.groups.upload(G.gh, st);
+    return;
+  }
+  // workspace [c^N; c] x c and the ID
+  G.gw.alloc(size_t(gw_off) * sizeof(T));
+  HIP_CHECK(hipMemsetAsync(G.gw.p, 0, G.gw.bytes, st));
+  G.tpool.alloc(size_t(t_off) * sizeof(T));
+  G.groups.upload(G.gh, st);
+  G.gsrcs.upload(gsrcs, st);
+  G.gtrips.upload(gtrips, st);
+  hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st, G.gw.as<T>(),
+                     G.base.as<T>(), G.groups.as<GroupDev>(), G.gsrcs.as<SrcDev>(),
+                     G.maps.as<int32_t>(), G.gtrips.as<TripDev>(), F.diag.as<double>(),
+                     F.offd.as<double>(), F.g.N);
+  HIP_CHECK(hipGetLastError());
+  G.perm_stride = ncmax;
+  G.kout.alloc(sizeof(int32_t) * G.ngroup);
+  G.perm.alloc(sizeof(int32_t) * size_t(G.ngroup) * ncmax);
+  const size_t smem = size_t(ncmax) * (sizeof(T) + 2 * sizeof(int));
+  if (smem > 64 * 1024) {
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
+  }
+  const double tau = sizeof(T) == 8 ? 1e-10 : 1e-5;
+  hipLaunchKernelGGL(k_cpqr<T>, dim3(G.ngroup), dim3(kThreads), smem, st, G.gw.as<T>(),
+                     G.tpool.as<T>(), G.groups.as<GroupDev>(), F.eps, tau, G.kout.as<int32_t>(),
+                     G.perm.as<int32_t>(), G.perm_stride);
+  HIP_CHECK(hipGetLastError());
+  std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
+  HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout.p, kh.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm.p, ph.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  // record skeletons; build the skeleton fronts
+  std::vector<FrontDev> ff;
+  std::vector<int32_t> idx;
+  G.gsel_h.clear();
+  int64_t fg_off = 0;
+  for (int gi = 0; gi < G.ngroup; ++gi) {
+    GroupDev& d = G.gh[gi];
+    int k = kh[gi];
+    if (k < 0 || k > d.nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
+    P.set_skeleton(l, gi, k, ph.data() + size_t(gi) * ncmax);
+    d.k = k;
+    d.skel = (k < d.nc) ? 1 : 0;
+    if (!d.skel) continue;
+    d.fg_off = fg_off;
+    FrontDev f{};
+    f.off = fg_off;
+    f.s = d.nc;
+    f.p = d.nc - k;
+    ff.push_back(f);
+    fg_off += int64_t(d.nc) * d.nc;
+    d.idx = int64_t(idx.size());
+    const Group& g = lev.groups[gi];
+    idx.insert(idx.end(), g.rd.begin(), g.rd.end());
+    idx.insert(idx.end(), g.sk.begin(), g.sk.end());
+    G.gsel_h.push_back(gi);
+  }
+  P.finish_groups(l);
+  G.nskel = int(G.gsel_h.size());
+  G.groups.upload(G.gh, st);
+  G.idx.upload(idx, st);
+  G.gsel.upload(G.gsel_h, st);
+  if (G.nskel == 0) return;
+  G.fg.alloc(size_t(fg_off) * sizeof(T));
+  HIP_CHECK(hipMemsetAsync(G.fg.p, 0, G.fg.bytes, st));
+  G.fgfronts.upload(ff, st);
+  G.info.alloc(sizeof(int) * ff.size());
+  HIP_CHECK(hipMemsetAsync(G.info.p, 0, G.info.bytes, st));
+  hipLaunchKernelGGL(k_group_front<T>, dim3(G.nskel), dim3(kThreads), 0, st, G.fg.as<T>(),
+                     G.gw.as<T>(), G.base.as<T>(), G.tpool.as<T>(), G.groups.as<GroupDev>(),
+                     G.perm.as<int32_t>(), G.perm_stride, G.gsel.as<int32_t>());
+  HIP_CHECK(hipGetLastError());
+  batched_ldl<T>(G.fg.as<T>(), ff, G.fgfronts.as<FrontDev>(), G.info.as<int>(), st);
+}
+
+// The solve kernels stage one right-hand side of a block in LDS.
+static void check_solve_lds(const hifde_factor_s& F) {
+  const size_t esz = F.prec == HIFDE_MIXED ? 4 : 8;
+  for (int l = 0; l <= F.g.L; ++l) {
+    const size_t e = l == F.g.L ? 8 : esz;
+    if (size_t(F.cl[l].pmax) * e > size_t(kSolveLdsBytes))
+      throw Error(HIFDE_EINVAL, "a cell eliminates more unknowns than the solve kernels stage");
+    if (l < F.g.L)
+      for (const GroupDev& g : F.gl[l].gh)
+        if (g.skel && size_t(g.nc) * e > size_t(kSolveLdsBytes))
+          throw Error(HIFDE_EINVAL, "a group is larger than the solve kernels stage");
+  }
+}
+
+template <typename T>
+static void run_factor(hifde_factor_s& F, hipStream_t st) {
+  const int L = F.g.L;
+  for (int l = 0; l < L; ++l) {
+    cells_level<T, T>(F, l, st);
+    if (!F.plan_only) check_info(F.cl[l].info, F.cl[l].fh.size(), "cell", l, st);
+    groups_level<T>(F, l, st);
+    if (!F.plan_only && F.gl[l].nskel > 0)
+      check_info(F.gl[l].info, size_t(F.gl[l].nskel), "group", l, st);
+  }
+  cells_level<double, T>(F, L, st);
+  if (!F.plan_only) {
+    check_info(F.cl[L].info, F.cl[L].fh.size(), "top block", L, st);
+    check_solve_lds(F);
+  }
+}
+
+static void fill_stats(hifde_factor_s& F) {
+  hifde_stats_t& s = F.stats;
+  const Planner& P = *F.planner;
+  s.N = F.g.N;
+  s.dim = F.g.dim;
+  s.levels = F.g.L;
+  double flops = 0.0, bytes = 0.0;
+  int64_t mbytes = 0;
+  const size_t esz = F.prec == HIFDE_MIXED ? 4 : 8;
+  for (int l = 0; l <= F.g.L && l < HIFDE_MAX_LEVELS; ++l) {
+    const Level& lev = P.levels()[l];
+    s.cells[l] = int64_t(lev.cells.size());
+    int mf = 0;
+    const size_t e = (l == F.g.L) ? 8 : esz;
+    for (const Cell& c : lev.cells) {
+      const double p = double(c.p.size()), q = double(c.q.size());
+      flops += p * p * p / 3.0 + p * p * q + p * q * q;
+      mf = std::max(mf, int(c.p.size() + c.q.size()));
+      const double stored = p * (p + 1) / 2 + p * q;  // [L\D; W^T]
+      bytes += 2.0 * stored * e;
+      mbytes += int64_t(stored * e) + int64_t(4 * (p + q));
+    }
+    s.max_front[l] = mf;
+    if (l == F.g.L) {
+      s.top_size = lev.cells.empty() ? 0 : int64_t(lev.cells[0].p.size());
+      continue;
+    }
+    s.groups[l] = int64_t(lev.groups.size());
+    int64_t in = 0, out = 0;
+    for (const Group& g : lev.groups) {
+      in += int64_t(g.c.size());
+      const double k = double(g.skel ? g.sk.size() : g.c.size());
+      const double r = double(g.c.size()) - k;
+      out += int64_t(k);
+      if (g.skel) {
+        flops += 2.0 * double(g.cN.size()) * double(g.c.size()) * k + r * r * r / 3.0 +
+                 5.0 * k * r * r + 4.0 * k * k * r;
+        const double stored = k * r + r * (r + 1) / 2 + k * r;  // T, [L_r\D_r; W_r^T]
+        bytes += 2.0 * stored * esz;
+        mbytes += int64_t(stored * esz) + int64_t(4 * g.c.size());
+      }
+    }
+    s.skel_in[l] = in;
+    s.skel_out[l] = out;
+  }
+  s.factor_flops = flops;
+  s.solve_bytes = bytes;
+  s.factor_bytes = mbytes;
+}
+
+// ---------------------------------------------------------------------------
+// F^-1 application on unknown-major vectors X (type TX).
+// ---------------------------------------------------------------------------
+template <typename T, typename TX>
+static void apply_inverse(hifde_factor_s& F, TX* X, int nrhs, hipStream_t st) {
+  const int L = F.g.L;
+  const size_t smem = kSolveLdsBytes;
+  for (int l = 0; l < L; ++l) {
+    CellLevelDev& C = F.cl[l];
+    for (int color = 0; color < 2; ++color)
+      hipLaunchKernelGGL((k_cell_up<T, TX>), dim3(C.ncell), dim3(kThreads), smem, st, X, nrhs,
+                         C.pool.as<T>(), C.fronts.as<FrontDev>(), C.idx.as<int32_t>(), color);
+    GroupLevelDev& G = F.gl[l];
+    if (G.nskel > 0)
+      hipLaunchKernelGGL((k_group_up<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
+                         G.fg.as<T>(), G.tpool.as<T>(), G.groups.as<GroupDev>(),
+                         G.gsel.as<int32_t>(), G.idx.as<int32_t>());
+  }
+  CellLevelDev& top = F.cl[L];
+  hipLaunchKernelGGL((k_cell_up<double, TX>), dim3(top.ncell), dim3(kThreads), smem, st, X, nrhs,
+                     top.pool.as<double>(), top.fronts.as<FrontDev>(), top.idx.as<int32_t>(), -1);
+  hipLaunchKernelGGL((k_cell_down<double, TX>), dim3(top.ncell), dim3(kThreads), smem, st, X,
+                     nrhs, top.pool.as<double>(), top.fronts.as<FrontDev>(),
+                     top.idx.as<int32_t>());
+  for (int l = L - 1; l >= 0; --l) {
+    GroupLevelDev& G = F.gl[l];
+    if (G.nskel > 0)
+      hipLaunchKernelGGL((k_group_down<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
+                         G.fg.as<T>(), G.tpool.as<T>(), G.groups.as<GroupDev>(),
+                         G.gsel.as<int32_t>(), G.idx.as<int32_t>());
+    CellLevelDev& C = F.cl[l];
+    hipLaunchKernelGGL((k_cell_down<T, TX>), dim3(C.ncell), dim3(kThreads), smem, st, X, nrhs,
+                       C.pool.as<T>(), C.fronts.as<FrontDev>(), C.idx.as<int32_t>());
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
+  const size_t need = size_t(F.g.N) * size_t(nrhs) * 8;
+  if (F.X.bytes < need) F.X.alloc(need);
+  F.X_rhs = nrhs;
+}
+
+// z = F^-1 r for double unknown-major vectors.
+static void precond(hifde_factor_s& F, const double* r, double* z, int nrhs, hipStream_t st) {
+  const int64_t n = F.g.N * int64_t(nrhs);
+  if (F.prec == HIFDE_MIXED) {
+    ensure_X(F, nrhs);
+    float* Xf = F.X.as<float>();
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(kThreads), 0, st, n, r, Xf);
+    apply_inverse<float, float>(F, Xf, nrhs, st);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n)), dim3(kThreads), 0, st, n, Xf, z);
+  } else {
+    if (z != r) HIP_CHECK(hipMemcpyAsync(z, r, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
+    apply_inverse<double, double>(F, z, nrhs, st);
+  }
+}
+
+}  // namespace hifde
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* hifde_last_error(void) { return g_last_error.c_str(); }
+
+int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels, hifde_tree_t* out) {
+  if (!out) return fail(HIFDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  Geom g;
+  std::string err = check_geom(dim, n, leaf, skip_levels, &g);
+  if (!err.empty()) return fail(HIFDE_EINVAL, err);
+  return guarded([&] {
+    auto* t = new hifde_tree_s;
+    t->g = g;
+    *out = t;
+  });
+}
+
+void hifde_tree_free(hifde_tree_t tree) { delete tree; }
+
+void hifde_factor_free(hifde_factor_t F) { delete F; }
+
+int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, double eps,
+                 hifde_precision prec, uint32_t flags, void* hip_stream, hifde_factor_t* out) {
+  (void)flags;
+  if (!out) return fail(HIFDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!tree || !a) return fail(HIFDE_EINVAL, "tree or a is NULL");
+  if (!(eps >= 0.0 && eps < 1.0)) return fail(HIFDE_EINVAL, "eps must lie in [0, 1)");
+  if (prec != HIFDE_FP64 && prec != HIFDE_MIXED) return fail(HIFDE_EINVAL, "unknown precision");
+  for (int k = 0; k < tree->g.dim; ++k)
+    if (!a[k]) return fail(HIFDE_EINVAL, "a[k] is NULL");
+  std::unique_ptr<hifde_factor_s> F(new hifde_factor_s);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int rc = guarded([&] {
+    auto t0 = std::chrono::steady_clock::now();
+    F->g = tree->g;
+    F->prec = prec;
+    F->eps = eps;
+    F->planner.reset(new Planner(F->g));
+    F->cl.resize(F->g.L + 1);
+    F->gl.resize(F->g.L);
+    const int64_t N = F->g.N;
+    F->diag.alloc(size_t(N) * 8);
+    F->offd.alloc(size_t(N) * F->g.dim * 8);
+    DevMem aptr, bad;
+    std::vector<const double*> ah(a, a + F->g.dim);
+    aptr.upload(ah, st);
+    bad.alloc(sizeof(int));
+    HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_stencil, dim3(nblk(N)), dim3(kThreads), 0, st,
+                       aptr.as<const double* const>(), F->g.dim, F->g.n, N, b,
+                       F->diag.as<double>(), F->offd.as<double>(), bad.as<int>());
+    HIP_CHECK(hipGetLastError());
+    int badh = 0;
+    HIP_CHECK(hipMemcpyAsync(&badh, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (badh & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
+    if (badh & 2) throw Error(HIFDE_EINVAL, "b must be finite");
+    if (prec == HIFDE_MIXED) run_factor<float>(*F, st);
+    else run_factor<double>(*F, st);
+    HIP_CHECK(hipStreamSynchronize(st));
+    fill_stats(*F);
+    F->stats.factor_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (rc == HIFDE_OK) *out = F.release();
+  return rc;
+}
+
+int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level, hifde_factor_t* out) {
+  if (!out) return fail(HIFDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!tree || !redundant_level) return fail(HIFDE_EINVAL, "tree or redundant_level is NULL");
+  std::unique_ptr<hifde_factor_s> F(new hifde_factor_s);
+  int rc = guarded([&] {
+    F->g = tree->g;
+    F->plan_only = true;
+    F->planner.reset(new Planner(F->g));
+    F->cl.resize(F->g.L + 1);
+    F->gl.resize(F->g.L);
+    Planner& P = *F->planner;
+    for (int l = 0; l < F->g.L; ++l) {
+      P.plan_cells(l);
+      P.plan_groups(l, true);
+      auto& groups = P.levels()[l].groups;
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        std::vector<int32_t> sk;
+        for (int32_t i = 0; i < int32_t(groups[gi].c.size()); ++i)
+          if (redundant_level[groups[gi].c[i]] != 2 * l + 1) sk.push_back(i);
+        P.set_skeleton(l, int(gi), int(sk.size()), sk.data());
+      }
+      P.finish_groups(l);
+    }
+    P.plan_cells(F->g.L);
+    F->prec = HIFDE_FP64;
+    fill_stats(*F);
+  });
+  if (rc == HIFDE_OK) *out = F.release();
+  return rc;
+}
+
+int hifde_stats(hifde_factor_t F, hifde_stats_t* out) {
+  if (!F || !out) return fail(HIFDE_EINVAL, "NULL argument");
+  *out = F->stats;
+  return HIFDE_OK;
+}
+
+int hifde_export_sets(hifde_factor_t F, int level2, hifde_sets_t* out) {
+  if (!F || !out) return fail(HIFDE_EINVAL, "NULL argument");
+  const int L = F->g.L;
+  if (level2 < 0 || level2 > 2 * L) return fail(HIFDE_EINVAL, "level2 out of range");
+  return guarded([&] {
+    const Level& lev = F->planner->levels()[level2 / 2];
+    std::vector<int64_t> ids;
+    std::vector<const std::vector<int32_t>*> lists[4];
+    std::vector<int32_t> empty;
+    if (level2 % 2 == 0) {
+      for (const Cell& c : lev.cells) {
+        ids.push_back(c.cid);
+        lists[0].push_back(&c.p);
+        lists[1].push_back(&c.q);
+        lists[2].push_back(&empty);
+        lists[3].push_back(&empty);
+      }
+    } else {
+      for (const Group& g : lev.groups) {
+        ids.push_back(g.gid);
+        lists[0].push_back(&g.c);
+        lists[1].push_back(&g.cN);
+        lists[2].push_back(g.skel ? &g.sk : &g.c);
+        lists[3].push_back(g.skel ? &g.rd : &empty);
+      }
+    }
+    out->count = int64_t(ids.size());
+    for (int w = 0; w < 4; ++w) {
+      int64_t tot = 0;
+      for (auto* v : lists[w]) tot += int64_t(v->size());
+      out->total[w] = tot;
+    }
+    if (out->ids) std::copy(ids.begin(), ids.end(), out->ids);
+    for (int w = 0; w < 4; ++w) {
+      if (!out->offs[w] && !out->lists[w]) continue;
+      int64_t o = 0;
+      for (size_t i = 0; i < lists[w].size(); ++i) {
+        if (out->offs[w]) out->offs[w][i] = o;
+        if (out->lists[w]) std::copy(lists[w][i]->begin(), lists[w][i]->end(), out->lists[w] + o);
+        o += int64_t(lists[w][i]->size());
+      }
+      if (out->offs[w]) out->offs[w][lists[w].size()] = o;
+    }
+  });
+}
+
+int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, double* u,
+                int64_t ldu, void* hip_stream) {
+  if (!F || !f || !u) return fail(HIFDE_EINVAL, "NULL argument");
+  if (F->plan_only) return fail(HIFDE_ESTATE, "factor holds no numerical data");
+  if (nrhs < 1 || ldf < F->g.N || ldu < F->g.N) return fail(HIFDE_EINVAL, "bad nrhs or ld");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    const int64_t N = F->g.N, n = N * nrhs;
+    ensure_X(*F, nrhs);
+    if (F->prec == HIFDE_MIXED) {
+      float* X = F->X.as<float>();
+      hipLaunchKernelGGL(k_from_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
+                         f, ldf, X);
+      apply_inverse<float, float>(*F, X, int(nrhs), st);
+      hipLaunchKernelGGL(k_to_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
+                         X, u, ldu);
+    } else {
+      double* X = F->X.as<double>();
+      hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N,
+                         int(nrhs), f, ldf, X);
+      apply_inverse<double, double>(*F, X, int(nrhs), st);
+      hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N,
+                         int(nrhs), X, u, ldu);
+    }
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx, double* y,
+                 int64_t ldy, void* hip_stream) {
+  if (!F || !x || !y) return fail(HIFDE_EINVAL, "NULL argument");
+  if (F->plan_only) return fail(HIFDE_ESTATE, "factor holds no numerical data");
+  if (nrhs < 1 || ldx < F->g.N || ldy < F->g.N) return fail(HIFDE_EINVAL, "bad nrhs or ld");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    const int64_t N = F->g.N, n = N * nrhs;
+    DevMem a, b;
+    a.alloc(size_t(n) * 8);
+    b.alloc(size_t(n) * 8);
+    hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
+                       x, ldx, a.as<double>());
+    hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs), F->g.dim,
+                       F->g.n, F->diag.as<double>(), F->offd.as<double>(), a.as<double>(),
+                       b.as<double>());
+    hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
+                       b.as<double>(), y, ldy);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, double* u, int64_t ldu,
+              double tol, int maxit, int* iters, double* relres, void* hip_stream) {
+  if (!F || !f || !u || !iters || !relres) return fail(HIFDE_EINVAL, "NULL argument");
+  if (F->plan_only) return fail(HIFDE_ESTATE, "factor holds no numerical data");
+  if (nrhs < 1 || ldf < F->g.N || ldu < F->g.N) return fail(HIFDE_EINVAL, "bad nrhs or ld");
+  if (!(tol > 0.0) || maxit < 1) return fail(HIFDE_EINVAL, "tol must be > 0 and maxit >= 1");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  bool converged = true;
+  int rc = guarded([&] {
+    const int64_t N = F->g.N, n = N * nrhs;
+    const int nr = int(nrhs);
+    const bool flexible = F->prec == HIFDE_MIXED;
+    // vectors: x r z p Ap zold dz (unknown-major, double)
+    const int nvec = 7;
+    const size_t vbytes = size_t(n) * 8;
+    if (F->pcg_rhs != nrhs) {
+      F->pcg.alloc(vbytes * nvec + size_t(kDotBlocks) * 3 * nr * 8 + size_t(nr) * 8 * 12 +
+                   size_t(nr) * 4);
+      F->pcg_rhs = nrhs;
+    }
+    char* base = F->pcg.as<char>();
+    double* x = reinterpret_cast<double*>(base);
+    double* r = x + n;
+    double* z = r + n;
+    double* p = z + n;
+    double* Ap = p + n;
+    double* zold = Ap + n;
+    double* dz = zold + n;
+    double* partial = dz + n;
+    double* sc = partial + size_t(kDotBlocks) * 3 * nr;  // scalars
+    double* rz = sc;
+    double* pap = sc + nr;
+    double* alpha = sc + 2 * nr;
+    double* beta = sc + 3 * nr;
+    double* d3 = sc + 4 * nr;   // 3 x nr dot results
+    double* ff = sc + 7 * nr;   // ||f||^2
+    int* live = reinterpret_cast<int*>(sc + 12 * nr);
+    auto dots = [&](int np, const double* a0, const double* b0, const double* a1, const double* b1,
+                    const double* a2, const double* b2, double* outp) {
+      hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, st, N, nr, np, a0, b0,
+                         a1, b1, a2, b2, partial);
+      hipLaunchKernelGGL(k_dot_final, dim3(nblk(np * nr)), dim3(kThreads), 0, st, kDotBlocks, nr,
+                         np, partial, outp);
+    };
+    hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
+                       r);
+    HIP_CHECK(hipMemsetAsync(x, 0, vbytes, st));
+    std::vector<int> liveh(nr, 1), itsh(nr, 0);
+    std::vector<double> h3(3 * nr), fh(nr);
+    dots(1, r, r, nullptr, nullptr, nullptr, nullptr, ff);
+    HIP_CHECK(hipMemcpyAsync(fh.data(), ff, nr * 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int c = 0; c < nr; ++c) {
+      fh[c] = std::sqrt(fh[c]);
+      if (fh[c] == 0.0) liveh[c] = 0;
+    }
+    HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
+    precond(*F, r, z, nr, st);
+    HIP_CHECK(hipMemcpyAsync(p, z, vbytes, hipMemcpyDeviceToDevice, st));
+    if (flexible) HIP_CHECK(hipMemcpyAsync(zold, z, vbytes, hipMemcpyDeviceToDevice, st));
+    dots(1, r, z, nullptr, nullptr, nullptr, nullptr, rz);
+    int it = 0;
+    while (it < maxit) {
+      bool any = false;
+      for (int c = 0; c < nr; ++c) any = any || liveh[c];
+      if (!any) break;
+      ++it;
+      hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, F->g.dim, F->g.n,
+                         F->diag.as<double>(), F->offd.as<double>(), p, Ap);
+      dots(1, p, Ap, nullptr, nullptr, nullptr, nullptr, pap);
+      hipLaunchKernelGGL(k_pcg_alpha, dim3(nblk(nr)), dim3(kThreads), 0, st, nr, rz, pap, live, alpha);
+      hipLaunchKernelGGL(k_pcg_update_xr, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, alpha, p, Ap,
+                         x, r);
+      dots(1, r, r, nullptr, nullptr, nullptr, nullptr, d3);
+      HIP_CHECK(hipMemcpyAsync(h3.data(), d3, nr * 8, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      bool changed = false;
+      for (int c = 0; c < nr; ++c) {
+        if (!liveh[c]) continue;
+        itsh[c] = it;
+        if (std::sqrt(h3[c]) <= tol * fh[c]) {
+          liveh[c] = 0;
+          changed = true;
+        }
+      }
+      if (changed) HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
+      bool anyl = false;
+      for (int c = 0; c < nr; ++c) anyl = anyl || liveh[c];
+      if (!anyl || it == maxit) break;
+      precond(*F, r, z, nr, st);
+      if (flexible) {
+        hipLaunchKernelGGL(k_sub_and_copy, dim3(nblk(n)), dim3(kThreads), 0, st, n, z, zold, dz);
+        dots(2, r, dz, r, z, nullptr, nullptr, d3);
+      } else {
+        dots(2, r, z, r, z, nullptr, nullptr, d3);
+      }
+      hipLaunchKernelGGL(k_pcg_beta, dim3(nblk(nr)), dim3(kThreads), 0, st, nr, d3, d3 + nr, rz,
+                         live, beta);
+      hipLaunchKernelGGL(k_pcg_update_p, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, beta, live, z,
+                         p);
+    }
+    // true residuals
+    hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, F->g.dim, F->g.n,
+                       F->diag.as<double>(), F->offd.as<double>(), x, Ap);
+    hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
+                       r);
+    hipLaunchKernelGGL(k_sub_and_copy, dim3(nblk(n)), dim3(kThreads), 0, st, n, r, Ap, dz);
+    dots(1, dz, dz, nullptr, nullptr, nullptr, nullptr, d3);
+    HIP_CHECK(hipMemcpyAsync(h3.data(), d3, nr * 8, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, x, u,
+                       ldu);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int c = 0; c < nr; ++c) {
+      iters[c] = itsh[c];
+      relres[c] = fh[c] > 0 ? std::sqrt(h3[c]) / fh[c] : 0.0;
+      if (liveh[c]) converged = false;
+    }
+  });
+  if (rc != HIFDE_OK) return rc;
+  if (!converged) return fail(HIFDE_ENOCONV, "PCG did not reach the tolerance within maxit");
+  return HIFDE_OK;
+}
+
+}  // extern "C"
