@@ -7,16 +7,23 @@
 namespace hifde {
 
 // A symmetric block read by extend-add: column-major, only its lower
-// triangle is valid.  rowmap/colmap index the level's map array and give the
+// triangle is valid; it starts at element `off` of pool `pool` of the launch's
+// pool table.  rowmap/colmap index the level's map array and give the
 // destination row/column of every source index (-1 drops it).
 struct SrcDev {
-  const void* ptr;
+  int64_t off;
   int64_t ld;
   int32_t dim;
-  int32_t pad;
+  int32_t pool;
   int64_t rowmap;
   int64_t colmap;
 };
+
+// Base addresses of the pools the sources of one launch refer to.
+struct PoolTable {
+  const void* p[3];
+};
+enum : int32_t { POOL_CELLS = 0, POOL_BASE = 1, POOL_FG = 2 };
 
 // One loose stencil entry: destination (i, j) and the stencil value ref
 // (ref < N: diagonal of unknown ref; else offd[ref - N]).

@@ -57,7 +57,7 @@ struct DevMem {
   }
   ~DevMem() { release(); }
   void release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -68,28 +68,97 @@ struct DevMem {
     bytes = b;
   }
   template <class T> T* as() const { return static_cast<T*>(p); }
-  template <class T> void upload(const std::vector<T>& v, hipStream_t st) {
-    alloc(v.size() * sizeof(T));
-    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(p, v.data(), bytes, hipMemcpyHostToDevice, st));
+};
+
+// Bump allocator for the device buffers of one factorization: a few large
+// hipMalloc calls instead of one per array, all released together.
+struct Arena {
+  std::vector<DevMem> chunks;
+  size_t used = 0;
+  static constexpr size_t kChunk = size_t(256) << 20;
+  void* alloc(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (chunks.empty() || used + bytes > chunks.back().bytes) {
+      DevMem m;
+      m.alloc(std::max(bytes, kChunk));
+      chunks.push_back(std::move(m));
+      used = 0;
+    }
+    void* p = static_cast<char*>(chunks.back().p) + used;
+    used += bytes;
+    return p;
+  }
+  template <class T> T* get(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+  template <class T> T* upload(const std::vector<T>& v, hipStream_t st) {
+    T* d = get<T>(std::max<size_t>(1, v.size()));
+    if (!v.empty())
+      HIP_CHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return d;
   }
 };
 
-struct CellLevelDev {
-  DevMem pool;                  // frontal matrices
+// Device description of the cells of one level; depends on the plan only, so
+// the level-0 one is shared by every factorization of a tree.
+struct CellStatic {
   std::vector<FrontDev> fh;
-  DevMem fronts, srcs, maps, trips, idx, info;
+  std::vector<SrcDev> srcs_h;
+  std::vector<TripDev> trips_h;
+  std::vector<int32_t> idx_h;
+  const std::vector<int32_t>* maps_h = nullptr;
+  Arena mem;
+  FrontDev* fronts = nullptr;
+  SrcDev* srcs = nullptr;
+  int32_t* maps = nullptr;
+  TripDev* trips = nullptr;
+  int32_t* idx = nullptr;
   int64_t elems = 0;
   int pmax = 0, smax = 0, ncell = 0;
-  bool dbl = false;             // pool holds doubles (top block)
+  bool on_device = false;
 };
 
-struct GroupLevelDev {
-  std::vector<GroupDev> gh;
-  DevMem groups, bfronts, fgfronts, maps, bsrcs, btrips, gsrcs, gtrips;
-  DevMem gw, base, fg, tpool, kout, perm, gsel, idx, info;
+// Device description of the groups of one level (before the IDs).
+struct GroupStatic {
+  std::vector<GroupDev> gh;          // gw/base/t offsets, sizes, source ranges
+  std::vector<FrontDev> bf;          // base-formation "fronts"
+  std::vector<SrcDev> bsrcs_h, gsrcs_h;
+  std::vector<TripDev> btrips_h, gtrips_h;
+  const std::vector<int32_t>* maps_h = nullptr;
+  Arena mem;
+  FrontDev* bfronts = nullptr;
+  int32_t* maps = nullptr;
+  SrcDev* bsrcs = nullptr;
+  SrcDev* gsrcs = nullptr;
+  TripDev* btrips = nullptr;
+  TripDev* gtrips = nullptr;
+  int64_t base_elems = 0, gw_elems = 0, t_elems = 0;
+  int ncmax = 0;
+  bool on_device = false;
+};
+
+// Per-factorization state of one level.
+struct CellLevel {
+  std::shared_ptr<CellStatic> st;
+  void* pool = nullptr;              // frontal matrices
+  int* info = nullptr;
+  void* gscratch = nullptr;          // x staging for fronts too tall for LDS
+  int64_t gstride = 0;
+};
+
+struct GroupLevel {
+  std::shared_ptr<GroupStatic> st;
+  std::vector<GroupDev> gh;          // with k, skel, fg_off, idx filled in
+  GroupDev* groups = nullptr;
+  void *base = nullptr, *gw = nullptr, *fg = nullptr, *tpool = nullptr;
+  int32_t *kout = nullptr, *perm = nullptr, *gsel = nullptr, *idx = nullptr;
+  FrontDev* fgfronts = nullptr;
+  int* info = nullptr;
+  std::vector<FrontDev> ff;
+  std::vector<int32_t> gsel_h, idx_h;
   int64_t perm_stride = 0;
-  int nskel = 0, ngroup = 0;
-  std::vector<int32_t> gsel_h;
+  int nskel = 0, ngroup = 0, ncskel = 0;
+  void* gscratch = nullptr;
+  int64_t gstride = 0;
 };
 
 }  // namespace hifde
@@ -98,6 +167,10 @@ using namespace hifde;
 
 struct hifde_tree_s {
   Geom g;
+  std::shared_ptr<const LevelPlan> l0;      // level-0 cells and level-1/2 groups
+  std::shared_ptr<CellStatic> c0;           // their device descriptions
+  std::shared_ptr<GroupStatic> g0;
+  size_t c0_esz = 0;
 };
 
 struct hifde_factor_s {
@@ -106,13 +179,13 @@ struct hifde_factor_s {
   double eps = 0.0;
   bool plan_only = false;
   std::unique_ptr<Planner> planner;
-  std::vector<CellLevelDev> cl;   // L + 1 entries (last = top)
-  std::vector<GroupLevelDev> gl;  // L entries
+  std::vector<CellLevel> cl;   // L + 1 entries (last = top)
+  std::vector<GroupLevel> gl;  // L entries
+  Arena mem;
   DevMem diag, offd;
   hifde_stats_t stats{};
   // solver scratch
   DevMem X;
-  int64_t X_rhs = 0;
   DevMem pcg;
   int64_t pcg_rhs = 0;
 };
@@ -142,28 +215,27 @@ namespace hifde {
 static inline unsigned nblk(int64_t n, int t = kThreads) { return unsigned((n + t - 1) / t); }
 
 // ---------------------------------------------------------------------------
-// Source resolution: device address and leading dimension of a planned block.
+// Source resolution: pool and element offset of a planned block.
 // ---------------------------------------------------------------------------
-static SrcDev resolve(const hifde_factor_s& F, const Source& s, size_t esz) {
+static SrcDev resolve(const hifde_factor_s& F, const Source& s) {
   SrcDev d{};
   d.dim = s.dim;
   d.rowmap = s.rowmap;
   d.colmap = s.colmap;
   if (s.kind == SRC_CELL_U) {
-    const CellLevelDev& L = F.cl.at(s.level);
-    const FrontDev& f = L.fh.at(s.index);
-    const int64_t off = f.off + f.p + int64_t(f.p) * f.s;
-    d.ptr = static_cast<const char*>(L.pool.p) + off * int64_t(esz);
+    const FrontDev& f = F.cl.at(s.level).st->fh.at(s.index);
+    d.pool = POOL_CELLS;
+    d.off = f.off + f.p + int64_t(f.p) * f.s;
     d.ld = f.s;
   } else {
-    const GroupLevelDev& G = F.gl.at(s.level);
-    const GroupDev& g = G.gh.at(s.index);
+    const GroupDev& g = F.gl.at(s.level).gh.at(s.index);
     if (g.skel) {
       const int r = g.nc - g.k;
-      const int64_t off = g.fg_off + r + int64_t(r) * g.nc;
-      d.ptr = static_cast<const char*>(G.fg.p) + off * int64_t(esz);
+      d.pool = POOL_FG;
+      d.off = g.fg_off + r + int64_t(r) * g.nc;
     } else {
-      d.ptr = static_cast<const char*>(G.base.p) + g.base_off * int64_t(esz);
+      d.pool = POOL_BASE;
+      d.off = g.base_off;
     }
     d.ld = g.nc;
   }
@@ -172,6 +244,101 @@ static SrcDev resolve(const hifde_factor_s& F, const Source& s, size_t esz) {
 
 static void append_trips(std::vector<TripDev>& out, const std::vector<Trip>& in) {
   for (const Trip& t : in) out.push_back({t.i, t.j, t.ref});
+}
+
+static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, const LevelPlan& lp) {
+  auto cs = std::make_shared<CellStatic>();
+  int64_t off = 0;
+  for (const Cell& c : lp.cells) {
+    FrontDev f{};
+    f.off = off;
+    f.p = int32_t(c.p.size());
+    f.s = int32_t(c.p.size() + c.q.size());
+    f.src_begin = int32_t(cs->srcs_h.size());
+    for (const Source& s : c.src) cs->srcs_h.push_back(resolve(F, s));
+    f.src_end = int32_t(cs->srcs_h.size());
+    f.trip_begin = int64_t(cs->trips_h.size());
+    append_trips(cs->trips_h, c.trips);
+    f.trip_end = int64_t(cs->trips_h.size());
+    f.idx = int64_t(cs->idx_h.size());
+    cs->idx_h.insert(cs->idx_h.end(), c.p.begin(), c.p.end());
+    cs->idx_h.insert(cs->idx_h.end(), c.q.begin(), c.q.end());
+    f.color = c.color;
+    off += int64_t(f.s) * f.s;
+    cs->pmax = std::max(cs->pmax, f.p);
+    cs->smax = std::max(cs->smax, f.s);
+    cs->fh.push_back(f);
+  }
+  cs->elems = off;
+  cs->ncell = int(cs->fh.size());
+  cs->maps_h = &lp.maps;
+  return cs;
+}
+
+static void upload_cell_static(CellStatic& cs, hipStream_t st) {
+  if (cs.on_device) return;
+  cs.fronts = cs.mem.upload(cs.fh, st);
+  cs.srcs = cs.mem.upload(cs.srcs_h, st);
+  cs.maps = cs.mem.upload(*cs.maps_h, st);
+  cs.trips = cs.mem.upload(cs.trips_h, st);
+  cs.idx = cs.mem.upload(cs.idx_h, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+  cs.on_device = true;
+}
+
+static std::shared_ptr<GroupStatic> make_group_static(const hifde_factor_s& F,
+                                                      const LevelPlan& lp, bool skel) {
+  auto gs = std::make_shared<GroupStatic>();
+  int64_t base_off = 0, gw_off = 0, t_off = 0;
+  for (const Group& g : lp.groups) {
+    GroupDev d{};
+    d.nc = int32_t(g.c.size());
+    d.nn = int32_t(g.cN.size());
+    d.base_off = base_off;
+    d.gw_off = gw_off;
+    d.t_off = t_off;
+    FrontDev f{};
+    f.off = base_off;
+    f.s = d.nc;
+    f.p = 0;
+    f.src_begin = int32_t(gs->bsrcs_h.size());
+    for (const Source& s : g.bsrc) gs->bsrcs_h.push_back(resolve(F, s));
+    f.src_end = int32_t(gs->bsrcs_h.size());
+    f.trip_begin = int64_t(gs->btrips_h.size());
+    append_trips(gs->btrips_h, g.btrips);
+    f.trip_end = int64_t(gs->btrips_h.size());
+    gs->bf.push_back(f);
+    d.src_begin = int32_t(gs->gsrcs_h.size());
+    for (const Source& s : g.gsrc) gs->gsrcs_h.push_back(resolve(F, s));
+    d.src_end = int32_t(gs->gsrcs_h.size());
+    d.trip_begin = int64_t(gs->gtrips_h.size());
+    append_trips(gs->gtrips_h, g.gtrips);
+    d.trip_end = int64_t(gs->gtrips_h.size());
+    base_off += int64_t(d.nc) * d.nc;
+    if (skel) {
+      gw_off += (int64_t(d.nn) + d.nc) * d.nc;
+      t_off += int64_t(d.nc) * d.nc / 4 + 1;  // k (n-k) <= n^2/4
+    }
+    gs->ncmax = std::max(gs->ncmax, int(d.nc));
+    gs->gh.push_back(d);
+  }
+  gs->base_elems = base_off;
+  gs->gw_elems = gw_off;
+  gs->t_elems = t_off;
+  gs->maps_h = &lp.gmaps;
+  return gs;
+}
+
+static void upload_group_static(GroupStatic& gs, hipStream_t st) {
+  if (gs.on_device) return;
+  gs.bfronts = gs.mem.upload(gs.bf, st);
+  gs.maps = gs.mem.upload(*gs.maps_h, st);
+  gs.bsrcs = gs.mem.upload(gs.bsrcs_h, st);
+  gs.btrips = gs.mem.upload(gs.btrips_h, st);
+  gs.gsrcs = gs.mem.upload(gs.gsrcs_h, st);
+  gs.gtrips = gs.mem.upload(gs.gtrips_h, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+  gs.on_device = true;
 }
 
 // Batched partial LDL^T of a set of fronts already in `pool`.
@@ -202,65 +369,118 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
   HIP_CHECK(hipGetLastError());
 }
 
+// Replace each partially factored front's [L; W^T] by its apply form
+// B = [L^-1; W^T L^-1] (mirrored into the upper trapezoid) and D by D^-1.
+template <typename T>
+static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
+                       const FrontDev* fronts_d, hipStream_t st) {
+  if (fh.empty()) return;
+  const unsigned nf = unsigned(fh.size());
+  std::vector<int64_t> toff(fh.size());
+  int64_t tot = 0;
+  int pmax = 0;
+  for (size_t i = 0; i < fh.size(); ++i) {
+    toff[i] = tot;
+    tot += int64_t(fh[i].s) * kNB;
+    pmax = std::max(pmax, fh[i].p);
+  }
+  T* tmp = mem.get<T>(size_t(std::max<int64_t>(tot, 1)));
+  const int64_t* toff_d = mem.upload(toff, st);
+  for (int J = ((pmax - 1) / kNB) * kNB; J >= 0 && pmax > 0; J -= kNB) {
+    int64_t tiles = 0;
+    for (const auto& f : fh) {
+      if (J >= f.p) continue;
+      const int nb = std::min(kNB, f.p - J);
+      tiles = std::max<int64_t>(tiles, (f.s - J - nb + kIR - 1) / kIR);
+    }
+    if (tiles > 0) {
+      if (tiles > 65535) throw Error(HIFDE_EINVAL, "front too large for the inversion grid");
+      hipLaunchKernelGGL(k_inv_step<T>, dim3(nf, unsigned(tiles)), dim3(kThreads), 0, st, pool,
+                         fronts_d, J, tmp, toff_d);
+    }
+    hipLaunchKernelGGL(k_inv_commit<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
+                       toff_d);
+  }
+  hipLaunchKernelGGL(k_inv_finish<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d);
+  HIP_CHECK(hipGetLastError());
+}
+
+static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
+  PoolTable t{{nullptr, nullptr, nullptr}};
+  if (l_src < 0) return t;
+  t.p[POOL_CELLS] = F.cl[l_src].pool;
+  if (l_src < F.g.L) {
+    t.p[POOL_BASE] = F.gl[l_src].base;
+    t.p[POOL_FG] = F.gl[l_src].fg;
+  }
+  return t;
+}
+
+// Elements of x a solve work-group can stage in LDS.
+template <typename T>
+static int lds_x_capacity() {
+  return kSolveLdsBytes / int(sizeof(T));
+}
+
+// Scratch for solve kernels whose x does not fit in LDS.
+template <typename T>
+static void solve_scratch(Arena& mem, int nblocks, int smax, void** ptr, int64_t* stride) {
+  if (smax <= lds_x_capacity<T>()) return;
+  *stride = int64_t(smax) * kMaxRhsChunk;
+  *ptr = mem.get<T>(size_t(*stride) * std::max(1, nblocks));
+}
+
+// LDS sizing of one solve launch: x capacity (elements) and bytes.
+template <typename T>
+static void solve_lds(int smax, int nrhs, int* cap, size_t* bytes) {
+  const int cmax = lds_x_capacity<T>();
+  if (smax > cmax) {
+    *cap = cmax;
+  } else {
+    *cap = smax * rhs_chunk(smax, nrhs, cmax);
+  }
+  *bytes = size_t(*cap) * sizeof(T);
+}
+
 // ---------------------------------------------------------------------------
 // Cells of level l: plan, assemble, factor.
 // ---------------------------------------------------------------------------
 template <typename T, typename TS>
-static void cells_level(hifde_factor_s& F, int l, hipStream_t st) {
+static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
-  P.plan_cells(l);
-  const Level& lev = P.levels()[l];
-  CellLevelDev& D = F.cl[l];
-  D.dbl = sizeof(T) == 8;
-  D.fh.clear();
-  std::vector<SrcDev> srcs;
-  std::vector<TripDev> trips;
-  std::vector<int32_t> idx;
-  int64_t off = 0;
-  D.pmax = D.smax = 0;
-  for (const Cell& c : lev.cells) {
-    FrontDev f{};
-    f.off = off;
-    f.p = int32_t(c.p.size());
-    f.s = int32_t(c.p.size() + c.q.size());
-    f.src_begin = int32_t(srcs.size());
-    for (const Source& s : c.src) srcs.push_back(resolve(F, s, sizeof(TS)));
-    f.src_end = int32_t(srcs.size());
-    f.trip_begin = int64_t(trips.size());
-    append_trips(trips, c.trips);
-    f.trip_end = int64_t(trips.size());
-    f.idx = int64_t(idx.size());
-    idx.insert(idx.end(), c.p.begin(), c.p.end());
-    idx.insert(idx.end(), c.q.begin(), c.q.end());
-    f.color = c.color;
-    off += int64_t(f.s) * f.s;
-    D.pmax = std::max(D.pmax, f.p);
-    D.smax = std::max(D.smax, f.s);
-    D.fh.push_back(f);
+  CellLevel& D = F.cl[l];
+  if (l == 0 && tree->c0) {
+    D.st = tree->c0;
+  } else {
+    if (l > 0) P.plan_cells(l);
+    D.st = make_cell_static(F, *P.level(l).plan);
+    if (l == 0) {
+      tree->c0 = D.st;
+      tree->c0_esz = sizeof(T);
+    }
   }
-  D.elems = off;
-  D.ncell = int(D.fh.size());
   if (F.plan_only) return;
-  D.pool.alloc(size_t(off) * sizeof(T));
-  HIP_CHECK(hipMemsetAsync(D.pool.p, 0, D.pool.bytes, st));
-  D.fronts.upload(D.fh, st);
-  D.srcs.upload(srcs, st);
-  D.maps.upload(lev.maps, st);
-  D.trips.upload(trips, st);
-  D.idx.upload(idx, st);
-  D.info.alloc(sizeof(int) * std::max<size_t>(1, D.fh.size()));
-  HIP_CHECK(hipMemsetAsync(D.info.p, 0, D.info.bytes, st));
-  hipLaunchKernelGGL((k_assemble<T, TS>), dim3(D.ncell), dim3(kThreads), 0, st, D.pool.as<T>(),
-                     D.fronts.as<FrontDev>(), D.srcs.as<SrcDev>(), D.maps.as<int32_t>(),
-                     D.trips.as<TripDev>(), F.diag.as<double>(), F.offd.as<double>(), F.g.N);
+  CellStatic& S = *D.st;
+  upload_cell_static(S, st);
+  D.pool = F.mem.get<T>(size_t(S.elems));
+  HIP_CHECK(hipMemsetAsync(D.pool, 0, size_t(S.elems) * sizeof(T), st));
+  D.info = F.mem.get<int>(std::max(1, S.ncell));
+  HIP_CHECK(hipMemsetAsync(D.info, 0, sizeof(int) * std::max(1, S.ncell), st));
+  solve_scratch<T>(F.mem, S.ncell, S.smax + 4, &D.gscratch, &D.gstride);
+  PoolTable pt = pools_for_level(F, l - 1);
+  if (S.ncell > 0)
+    hipLaunchKernelGGL((k_assemble<T, TS>), dim3(S.ncell), dim3(kThreads), 0, st,
+                       static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps, S.trips,
+                       F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt);
   HIP_CHECK(hipGetLastError());
-  batched_ldl<T>(D.pool.as<T>(), D.fh, D.fronts.as<FrontDev>(), D.info.as<int>(), st);
+  batched_ldl<T>(static_cast<T*>(D.pool), S.fh, S.fronts, D.info, st);
+  apply_form<T>(F.mem, static_cast<T*>(D.pool), S.fh, S.fronts, st);
 }
 
-static void check_info(const DevMem& info, size_t n, const char* what, int l, hipStream_t st) {
+static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
   if (n == 0) return;
   std::vector<int> h(n);
-  HIP_CHECK(hipMemcpyAsync(h.data(), info.p, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(h.data(), info, n * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   for (size_t i = 0; i < n; ++i)
     if (h[i] != 0) {
@@ -275,108 +495,73 @@ static void check_info(const DevMem& info, size_t n, const char* what, int l, hi
 // Groups of level l+1/2: plan, base blocks, ID, skeleton fronts.
 // ---------------------------------------------------------------------------
 template <typename T>
-static void groups_level(hifde_factor_s& F, int l, hipStream_t st) {
+static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
   const bool skel = F.eps > 0.0 && l >= F.g.skip;
-  P.plan_groups(l, skel);
-  Level& lev = P.levels()[l];
-  GroupLevelDev& G = F.gl[l];
-  G.gh.clear();
-  G.ngroup = int(lev.groups.size());
-  std::vector<FrontDev> bf;
-  std::vector<SrcDev> bsrcs, gsrcs;
-  std::vector<TripDev> btrips, gtrips;
-  int64_t base_off = 0, gw_off = 0, t_off = 0;
-  int ncmax = 0;
-  for (const Group& g : lev.groups) {
-    GroupDev d{};
-    d.nc = int32_t(g.c.size());
-    d.nn = int32_t(g.cN.size());
-    d.base_off = base_off;
-    d.gw_off = gw_off;
-    d.t_off = t_off;
-    FrontDev f{};
-    f.off = base_off;
-    f.s = d.nc;
-    f.p = 0;
-    f.src_begin = int32_t(bsrcs.size());
-    for (const Source& s : g.bsrc) bsrcs.push_back(resolve(F, s, sizeof(T)));
-    f.src_end = int32_t(bsrcs.size());
-    f.trip_begin = int64_t(btrips.size());
-    append_trips(btrips, g.btrips);
-    f.trip_end = int64_t(btrips.size());
-    bf.push_back(f);
-    d.src_begin = int32_t(gsrcs.size());
-    for (const Source& s : g.gsrc) gsrcs.push_back(resolve(F, s, sizeof(T)));
-    d.src_end = int32_t(gsrcs.size());
-    d.trip_begin = int64_t(gtrips.size());
-    append_trips(gtrips, g.gtrips);
-    d.trip_end = int64_t(gtrips.size());
-    base_off += int64_t(d.nc) * d.nc;
-    if (skel) {
-      gw_off += (int64_t(d.nn) + d.nc) * d.nc;
-      t_off += int64_t(d.nc) * d.nc / 4 + 1;  // k (n-k) <= n^2/4
-    }
-    ncmax = std::max(ncmax, int(d.nc));
-    G.gh.push_back(d);
+  GroupLevel& G = F.gl[l];
+  P.plan_groups(l);
+  if (l == 0 && tree->g0 && (tree->g0->gw_elems > 0) == skel) {
+    G.st = tree->g0;
+  } else {
+    G.st = make_group_static(F, *P.level(l).plan, skel);
+    if (l == 0) tree->g0 = G.st;
   }
+  GroupStatic& S = *G.st;
+  G.gh = S.gh;
+  G.ngroup = int(G.gh.size());
+  const Level& lev = P.level(l);
   if (F.plan_only) return;
-  G.base.alloc(size_t(base_off) * sizeof(T));
-  HIP_CHECK(hipMemsetAsync(G.base.p, 0, G.base.bytes, st));
-  G.bfronts.upload(bf, st);
-  G.maps.upload(lev.maps, st);
-  G.bsrcs.upload(bsrcs, st);
-  G.btrips.upload(btrips, st);
+  upload_group_static(S, st);
+  G.base = F.mem.get<T>(size_t(S.base_elems));
+  HIP_CHECK(hipMemsetAsync(G.base, 0, size_t(S.base_elems) * sizeof(T), st));
+  PoolTable pt_prev = pools_for_level(F, l - 1);
   if (G.ngroup > 0) {
-    hipLaunchKernelGGL((k_assemble<T, T>), dim3(G.ngroup), dim3(kThreads), 0, st, G.base.as<T>(),
-                       G.bfronts.as<FrontDev>(), G.bsrcs.as<SrcDev>(), G.maps.as<int32_t>(),
-                       G.btrips.as<TripDev>(), F.diag.as<double>(), F.offd.as<double>(), F.g.N);
+    hipLaunchKernelGGL((k_assemble<T, T>), dim3(G.ngroup), dim3(kThreads), 0, st,
+                       static_cast<T*>(G.base), S.bfronts, S.bsrcs, S.maps, S.btrips,
+                       F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_prev);
     HIP_CHECK(hipGetLastError());
   }
   if (!skel || G.ngroup == 0) {
-    for (size_t gi = 0; gi < lev.groups.size(); ++gi) P.set_skeleton(l, int(gi), G.gh[gi].nc, nullptr);
+    for (int gi = 0; gi < G.ngroup; ++gi) P.set_skeleton(l, gi, G.gh[gi].nc, nullptr);
     P.finish_groups(l);
     G.nskel = 0;
-    G.groups.upload(G.gh, st);
     return;
   }
-  // workspace [c^N; c] x c and the ID
-  G.gw.alloc(size_t(gw_off) * sizeof(T));
-  HIP_CHECK(hipMemsetAsync(G.gw.p, 0, G.gw.bytes, st));
-  G.tpool.alloc(size_t(t_off) * sizeof(T));
-  G.groups.upload(G.gh, st);
-  G.gsrcs.upload(gsrcs, st);
-  G.gtrips.upload(gtrips, st);
-  hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st, G.gw.as<T>(),
-                     G.base.as<T>(), G.groups.as<GroupDev>(), G.gsrcs.as<SrcDev>(),
-                     G.maps.as<int32_t>(), G.gtrips.as<TripDev>(), F.diag.as<double>(),
-                     F.offd.as<double>(), F.g.N);
+  G.gw = F.mem.get<T>(size_t(S.gw_elems));
+  HIP_CHECK(hipMemsetAsync(G.gw, 0, size_t(S.gw_elems) * sizeof(T), st));
+  G.tpool = F.mem.get<T>(size_t(S.t_elems));
+  G.groups = F.mem.upload(G.gh, st);
+  PoolTable pt_cur{{F.cl[l].pool, nullptr, nullptr}};
+  hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
+                     static_cast<T*>(G.gw), static_cast<const T*>(G.base), G.groups, S.gsrcs,
+                     S.maps, S.gtrips, F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_cur);
   HIP_CHECK(hipGetLastError());
+  const int ncmax = S.ncmax;
   G.perm_stride = ncmax;
-  G.kout.alloc(sizeof(int32_t) * G.ngroup);
-  G.perm.alloc(sizeof(int32_t) * size_t(G.ngroup) * ncmax);
+  G.kout = F.mem.get<int32_t>(G.ngroup);
+  G.perm = F.mem.get<int32_t>(size_t(G.ngroup) * ncmax);
   const size_t smem = size_t(ncmax) * (sizeof(T) + 2 * sizeof(int));
-  if (smem > 64 * 1024) {
+  if (smem > 64 * 1024)
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
-  }
   const double tau = sizeof(T) == 8 ? 1e-10 : 1e-5;
-  hipLaunchKernelGGL(k_cpqr<T>, dim3(G.ngroup), dim3(kThreads), smem, st, G.gw.as<T>(),
-                     G.tpool.as<T>(), G.groups.as<GroupDev>(), F.eps, tau, G.kout.as<int32_t>(),
-                     G.perm.as<int32_t>(), G.perm_stride);
+  hipLaunchKernelGGL(k_cpqr<T>, dim3(G.ngroup), dim3(kThreads), smem, st, static_cast<T*>(G.gw),
+                     static_cast<T*>(G.tpool), G.groups, F.eps, tau, G.kout, G.perm,
+                     G.perm_stride);
   HIP_CHECK(hipGetLastError());
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
-  HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout.p, kh.size() * 4, hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm.p, ph.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   // record skeletons; build the skeleton fronts
-  std::vector<FrontDev> ff;
-  std::vector<int32_t> idx;
-  G.gsel_h.clear();
   int64_t fg_off = 0;
+  G.gsel_h.clear();
+  G.idx_h.clear();
+  G.ff.clear();
+  G.ncskel = 0;
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
-    int k = kh[gi];
+    const int k = kh[gi];
     if (k < 0 || k > d.nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
     P.set_skeleton(l, gi, k, ph.data() + size_t(gi) * ncmax);
     d.k = k;
@@ -387,61 +572,59 @@ static void groups_level(hifde_factor_s& F, int l, hipStream_t st) {
     f.off = fg_off;
     f.s = d.nc;
     f.p = d.nc - k;
-    ff.push_back(f);
+    G.ff.push_back(f);
     fg_off += int64_t(d.nc) * d.nc;
-    d.idx = int64_t(idx.size());
-    const Group& g = lev.groups[gi];
-    idx.insert(idx.end(), g.rd.begin(), g.rd.end());
-    idx.insert(idx.end(), g.sk.begin(), g.sk.end());
+    d.idx = int64_t(G.idx_h.size());
+    const GroupRes& R = lev.res[gi];
+    G.idx_h.insert(G.idx_h.end(), R.rd.begin(), R.rd.end());
+    G.idx_h.insert(G.idx_h.end(), R.sk.begin(), R.sk.end());
     G.gsel_h.push_back(gi);
+    G.ncskel = std::max(G.ncskel, int(d.nc));
   }
   P.finish_groups(l);
   G.nskel = int(G.gsel_h.size());
-  G.groups.upload(G.gh, st);
-  G.idx.upload(idx, st);
-  G.gsel.upload(G.gsel_h, st);
+  G.groups = F.mem.upload(G.gh, st);
   if (G.nskel == 0) return;
-  G.fg.alloc(size_t(fg_off) * sizeof(T));
-  HIP_CHECK(hipMemsetAsync(G.fg.p, 0, G.fg.bytes, st));
-  G.fgfronts.upload(ff, st);
-  G.info.alloc(sizeof(int) * ff.size());
-  HIP_CHECK(hipMemsetAsync(G.info.p, 0, G.info.bytes, st));
-  hipLaunchKernelGGL(k_group_front<T>, dim3(G.nskel), dim3(kThreads), 0, st, G.fg.as<T>(),
-                     G.gw.as<T>(), G.base.as<T>(), G.tpool.as<T>(), G.groups.as<GroupDev>(),
-                     G.perm.as<int32_t>(), G.perm_stride, G.gsel.as<int32_t>());
+  G.idx = F.mem.upload(G.idx_h, st);
+  G.gsel = F.mem.upload(G.gsel_h, st);
+  G.fg = F.mem.get<T>(size_t(fg_off));
+  HIP_CHECK(hipMemsetAsync(G.fg, 0, size_t(fg_off) * sizeof(T), st));
+  G.fgfronts = F.mem.upload(G.ff, st);
+  G.info = F.mem.get<int>(G.ff.size());
+  HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ff.size(), st));
+  solve_scratch<T>(F.mem, G.nskel, 2 * G.ncskel + 4, &G.gscratch, &G.gstride);
+  hipLaunchKernelGGL(k_group_front<T>, dim3(G.nskel), dim3(kThreads), 0, st,
+                     static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
+                     static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
+                     G.perm, G.perm_stride, G.gsel);
   HIP_CHECK(hipGetLastError());
-  batched_ldl<T>(G.fg.as<T>(), ff, G.fgfronts.as<FrontDev>(), G.info.as<int>(), st);
-}
-
-// The solve kernels stage one right-hand side of a block in LDS.
-static void check_solve_lds(const hifde_factor_s& F) {
-  const size_t esz = F.prec == HIFDE_MIXED ? 4 : 8;
-  for (int l = 0; l <= F.g.L; ++l) {
-    const size_t e = l == F.g.L ? 8 : esz;
-    if (size_t(F.cl[l].pmax) * e > size_t(kSolveLdsBytes))
-      throw Error(HIFDE_EINVAL, "a cell eliminates more unknowns than the solve kernels stage");
-    if (l < F.g.L)
-      for (const GroupDev& g : F.gl[l].gh)
-        if (g.skel && size_t(g.nc) * e > size_t(kSolveLdsBytes))
-          throw Error(HIFDE_EINVAL, "a group is larger than the solve kernels stage");
-  }
+  batched_ldl<T>(static_cast<T*>(G.fg), G.ff, G.fgfronts, G.info, st);
+  apply_form<T>(F.mem, static_cast<T*>(G.fg), G.ff, G.fgfronts, st);
 }
 
 template <typename T>
-static void run_factor(hifde_factor_s& F, hipStream_t st) {
+static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   const int L = F.g.L;
+  Planner& P = *F.planner;
+  // Level 0 and its groups depend on the geometry only: plan once per tree.
+  if (!tree->l0) {
+    P.plan_cells(0);
+    P.plan_groups(0);
+    tree->l0 = P.level0();
+    tree->c0.reset();
+    tree->g0.reset();
+  } else {
+    P.adopt_level0(tree->l0);
+  }
   for (int l = 0; l < L; ++l) {
-    cells_level<T, T>(F, l, st);
-    if (!F.plan_only) check_info(F.cl[l].info, F.cl[l].fh.size(), "cell", l, st);
-    groups_level<T>(F, l, st);
+    cells_level<T, T>(F, tree, l, st);
+    if (!F.plan_only) check_info(F.cl[l].info, F.cl[l].st->fh.size(), "cell", l, st);
+    groups_level<T>(F, tree, l, st);
     if (!F.plan_only && F.gl[l].nskel > 0)
       check_info(F.gl[l].info, size_t(F.gl[l].nskel), "group", l, st);
   }
-  cells_level<double, T>(F, L, st);
-  if (!F.plan_only) {
-    check_info(F.cl[L].info, F.cl[L].fh.size(), "top block", L, st);
-    check_solve_lds(F);
-  }
+  cells_level<double, T>(F, tree, L, st);
+  if (!F.plan_only) check_info(F.cl[L].info, F.cl[L].st->fh.size(), "top block", L, st);
 }
 
 static void fill_stats(hifde_factor_s& F) {
@@ -454,11 +637,11 @@ static void fill_stats(hifde_factor_s& F) {
   int64_t mbytes = 0;
   const size_t esz = F.prec == HIFDE_MIXED ? 4 : 8;
   for (int l = 0; l <= F.g.L && l < HIFDE_MAX_LEVELS; ++l) {
-    const Level& lev = P.levels()[l];
-    s.cells[l] = int64_t(lev.cells.size());
+    const Level& lev = P.level(l);
+    s.cells[l] = int64_t(lev.cells().size());
     int mf = 0;
     const size_t e = (l == F.g.L) ? 8 : esz;
-    for (const Cell& c : lev.cells) {
+    for (const Cell& c : lev.cells()) {
       const double p = double(c.p.size()), q = double(c.q.size());
       flops += p * p * p / 3.0 + p * p * q + p * q * q;
       mf = std::max(mf, int(c.p.size() + c.q.size()));
@@ -468,17 +651,19 @@ static void fill_stats(hifde_factor_s& F) {
     }
     s.max_front[l] = mf;
     if (l == F.g.L) {
-      s.top_size = lev.cells.empty() ? 0 : int64_t(lev.cells[0].p.size());
+      s.top_size = lev.cells().empty() ? 0 : int64_t(lev.cells()[0].p.size());
       continue;
     }
-    s.groups[l] = int64_t(lev.groups.size());
+    s.groups[l] = int64_t(lev.groups().size());
     int64_t in = 0, out = 0;
-    for (const Group& g : lev.groups) {
+    for (size_t gi = 0; gi < lev.groups().size(); ++gi) {
+      const Group& g = lev.groups()[gi];
+      const GroupRes& R = lev.res[gi];
       in += int64_t(g.c.size());
-      const double k = double(g.skel ? g.sk.size() : g.c.size());
+      const double k = double(R.skel ? R.sk.size() : g.c.size());
       const double r = double(g.c.size()) - k;
       out += int64_t(k);
-      if (g.skel) {
+      if (R.skel) {
         flops += 2.0 * double(g.cN.size()) * double(g.c.size()) * k + r * r * r / 3.0 +
                  5.0 * k * r * r + 4.0 * k * k * r;
         const double stored = k * r + r * (r + 1) / 2 + k * r;  // T, [L_r\D_r; W_r^T]
@@ -500,33 +685,45 @@ static void fill_stats(hifde_factor_s& F) {
 template <typename T, typename TX>
 static void apply_inverse(hifde_factor_s& F, TX* X, int nrhs, hipStream_t st) {
   const int L = F.g.L;
-  const size_t smem = kSolveLdsBytes;
+  int cap;
+  size_t smem;
   for (int l = 0; l < L; ++l) {
-    CellLevelDev& C = F.cl[l];
+    CellLevel& C = F.cl[l];
+    const CellStatic& S = *C.st;
+    solve_lds<T>(S.smax + 4, nrhs, &cap, &smem);
     for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL((k_cell_up<T, TX>), dim3(C.ncell), dim3(kThreads), smem, st, X, nrhs,
-                         C.pool.as<T>(), C.fronts.as<FrontDev>(), C.idx.as<int32_t>(), color);
-    GroupLevelDev& G = F.gl[l];
-    if (G.nskel > 0)
+      hipLaunchKernelGGL((k_cell_up<T, TX>), dim3(S.ncell), dim3(kThreads), smem, st, X, nrhs,
+                         static_cast<const T*>(C.pool), S.fronts, S.idx, color, cap,
+                         static_cast<T*>(C.gscratch), C.gstride);
+    GroupLevel& G = F.gl[l];
+    if (G.nskel > 0) {
+      solve_lds<T>(2 * G.ncskel + 4, nrhs, &cap, &smem);
       hipLaunchKernelGGL((k_group_up<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
-                         G.fg.as<T>(), G.tpool.as<T>(), G.groups.as<GroupDev>(),
-                         G.gsel.as<int32_t>(), G.idx.as<int32_t>());
+                         static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool), G.groups,
+                         G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+    }
   }
-  CellLevelDev& top = F.cl[L];
-  hipLaunchKernelGGL((k_cell_up<double, TX>), dim3(top.ncell), dim3(kThreads), smem, st, X, nrhs,
-                     top.pool.as<double>(), top.fronts.as<FrontDev>(), top.idx.as<int32_t>(), -1);
-  hipLaunchKernelGGL((k_cell_down<double, TX>), dim3(top.ncell), dim3(kThreads), smem, st, X,
-                     nrhs, top.pool.as<double>(), top.fronts.as<FrontDev>(),
-                     top.idx.as<int32_t>());
+  CellLevel& top = F.cl[L];
+  solve_lds<double>(top.st->smax + 4, nrhs, &cap, &smem);
+  hipLaunchKernelGGL((k_cell_up<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st, X,
+                     nrhs, static_cast<const double*>(top.pool), top.st->fronts, top.st->idx, -1,
+                     cap, static_cast<double*>(top.gscratch), top.gstride);
+  hipLaunchKernelGGL((k_cell_down<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st, X,
+                     nrhs, static_cast<const double*>(top.pool), top.st->fronts, top.st->idx, cap,
+                     static_cast<double*>(top.gscratch), top.gstride);
   for (int l = L - 1; l >= 0; --l) {
-    GroupLevelDev& G = F.gl[l];
-    if (G.nskel > 0)
+    GroupLevel& G = F.gl[l];
+    if (G.nskel > 0) {
+      solve_lds<T>(2 * G.ncskel + 4, nrhs, &cap, &smem);
       hipLaunchKernelGGL((k_group_down<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
-                         G.fg.as<T>(), G.tpool.as<T>(), G.groups.as<GroupDev>(),
-                         G.gsel.as<int32_t>(), G.idx.as<int32_t>());
-    CellLevelDev& C = F.cl[l];
-    hipLaunchKernelGGL((k_cell_down<T, TX>), dim3(C.ncell), dim3(kThreads), smem, st, X, nrhs,
-                       C.pool.as<T>(), C.fronts.as<FrontDev>(), C.idx.as<int32_t>());
+                         static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool), G.groups,
+                         G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+    }
+    CellLevel& C = F.cl[l];
+    solve_lds<T>(C.st->smax + 4, nrhs, &cap, &smem);
+    hipLaunchKernelGGL((k_cell_down<T, TX>), dim3(C.st->ncell), dim3(kThreads), smem, st, X, nrhs,
+                       static_cast<const T*>(C.pool), C.st->fronts, C.st->idx, cap,
+                       static_cast<T*>(C.gscratch), C.gstride);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -534,7 +731,6 @@ static void apply_inverse(hifde_factor_s& F, TX* X, int nrhs, hipStream_t st) {
 static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
   const size_t need = size_t(F.g.N) * size_t(nrhs) * 8;
   if (F.X.bytes < need) F.X.alloc(need);
-  F.X_rhs = nrhs;
 }
 
 // z = F^-1 r for double unknown-major vectors.
@@ -601,22 +797,21 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     const int64_t N = F->g.N;
     F->diag.alloc(size_t(N) * 8);
     F->offd.alloc(size_t(N) * F->g.dim * 8);
-    DevMem aptr, bad;
+    const double** aptr = F->mem.get<const double*>(F->g.dim);
+    int* bad = F->mem.get<int>(1);
     std::vector<const double*> ah(a, a + F->g.dim);
-    aptr.upload(ah, st);
-    bad.alloc(sizeof(int));
-    HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_stencil, dim3(nblk(N)), dim3(kThreads), 0, st,
-                       aptr.as<const double* const>(), F->g.dim, F->g.n, N, b,
-                       F->diag.as<double>(), F->offd.as<double>(), bad.as<int>());
+    HIP_CHECK(hipMemcpyAsync(aptr, ah.data(), ah.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_stencil, dim3(nblk(N)), dim3(kThreads), 0, st, aptr, F->g.dim, F->g.n, N, b,
+                       F->diag.as<double>(), F->offd.as<double>(), bad);
     HIP_CHECK(hipGetLastError());
     int badh = 0;
-    HIP_CHECK(hipMemcpyAsync(&badh, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     if (badh & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
     if (badh & 2) throw Error(HIFDE_EINVAL, "b must be finite");
-    if (prec == HIFDE_MIXED) run_factor<float>(*F, st);
-    else run_factor<double>(*F, st);
+    if (prec == HIFDE_MIXED) run_factor<float>(*F, tree, st);
+    else run_factor<double>(*F, tree, st);
     HIP_CHECK(hipStreamSynchronize(st));
     fill_stats(*F);
     F->stats.factor_ms =
@@ -635,13 +830,11 @@ int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level, hifde_f
     F->g = tree->g;
     F->plan_only = true;
     F->planner.reset(new Planner(F->g));
-    F->cl.resize(F->g.L + 1);
-    F->gl.resize(F->g.L);
     Planner& P = *F->planner;
     for (int l = 0; l < F->g.L; ++l) {
       P.plan_cells(l);
-      P.plan_groups(l, true);
-      auto& groups = P.levels()[l].groups;
+      P.plan_groups(l);
+      const auto& groups = P.level(l).groups();
       for (size_t gi = 0; gi < groups.size(); ++gi) {
         std::vector<int32_t> sk;
         for (int32_t i = 0; i < int32_t(groups[gi].c.size()); ++i)
@@ -669,12 +862,12 @@ int hifde_export_sets(hifde_factor_t F, int level2, hifde_sets_t* out) {
   const int L = F->g.L;
   if (level2 < 0 || level2 > 2 * L) return fail(HIFDE_EINVAL, "level2 out of range");
   return guarded([&] {
-    const Level& lev = F->planner->levels()[level2 / 2];
+    const Level& lev = F->planner->level(level2 / 2);
     std::vector<int64_t> ids;
     std::vector<const std::vector<int32_t>*> lists[4];
     std::vector<int32_t> empty;
     if (level2 % 2 == 0) {
-      for (const Cell& c : lev.cells) {
+      for (const Cell& c : lev.cells()) {
         ids.push_back(c.cid);
         lists[0].push_back(&c.p);
         lists[1].push_back(&c.q);
@@ -682,12 +875,14 @@ int hifde_export_sets(hifde_factor_t F, int level2, hifde_sets_t* out) {
         lists[3].push_back(&empty);
       }
     } else {
-      for (const Group& g : lev.groups) {
+      for (size_t gi = 0; gi < lev.groups().size(); ++gi) {
+        const Group& g = lev.groups()[gi];
+        const GroupRes& R = lev.res[gi];
         ids.push_back(g.gid);
         lists[0].push_back(&g.c);
         lists[1].push_back(&g.cN);
-        lists[2].push_back(g.skel ? &g.sk : &g.c);
-        lists[3].push_back(g.skel ? &g.rd : &empty);
+        lists[2].push_back(R.skel ? &R.sk : &g.c);
+        lists[3].push_back(R.skel ? &R.rd : &empty);
       }
     }
     out->count = int64_t(ids.size());
@@ -802,8 +997,8 @@ int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, doub
                     const double* a2, const double* b2, double* outp) {
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, st, N, nr, np, a0, b0,
                          a1, b1, a2, b2, partial);
-      hipLaunchKernelGGL(k_dot_final, dim3(nblk(np * nr)), dim3(kThreads), 0, st, kDotBlocks, nr,
-                         np, partial, outp);
+      hipLaunchKernelGGL(k_dot_final, dim3(np * nr), dim3(kThreads), 0, st, kDotBlocks, nr, np,
+                         partial, outp);
     };
     hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
                        r);

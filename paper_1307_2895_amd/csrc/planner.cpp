@@ -36,31 +36,41 @@ Planner::Planner(const Geom& g) : g_(g) {
   active_.assign(g_.N, 1);
   grouped_.assign(g_.N, 0);
   loc_.assign(g_.N, -1);
+  own0_.assign(g_.N, -1);
+  own1_.assign(g_.N, -1);
+  act_.resize(g_.N);
+  for (int64_t d = 0; d < g_.N; ++d) act_[d] = int32_t(d);
   lv_.resize(g_.L + 1);
-}
-
-int64_t Planner::active_count() const {
-  int64_t c = 0;
-  for (auto a : active_) c += a;
-  return c;
+  // x lies on a level-l separator iff (x+1) mod (m 2^l) == 0 and x != n-1;
+  // these sets are nested, so one number per coordinate describes them.
+  seplev_.assign(g_.n, -1);
+  for (int64_t x = 0; x < g_.n; ++x)
+    for (int l = 0; l < g_.L; ++l) {
+      const int64_t M = g_.m << l;
+      if ((x + 1) % M == 0 && x != g_.n - 1) seplev_[x] = int8_t(l);
+    }
 }
 
 void Planner::coords(int64_t d, int64_t* x) const {
-  for (int k = 0; k < g_.dim; ++k) x[k] = (d / g_.stride[k]) % g_.n;
+  x[0] = d % g_.n;
+  if (g_.dim > 1) x[1] = (d / g_.n) % g_.n;
+  if (g_.dim > 2) x[2] = d / (g_.n * g_.n);
 }
 
-int Planner::sigma(int64_t d, int64_t M) const {
+int Planner::sigma(int64_t d, int l) const {
   int64_t x[3];
   coords(d, x);
   int s = 0;
-  for (int k = 0; k < g_.dim; ++k) s += is_sep(x[k], M) ? 1 : 0;
+  for (int k = 0; k < g_.dim; ++k) s += seplev_[x[k]] >= l ? 1 : 0;
   return s;
 }
 
-int64_t Planner::box_of(int64_t d, int64_t M) const {
+int64_t Planner::box_of(int64_t d, int l) const {
+  if (l >= g_.L) return 0;
   int64_t x[3];
   coords(d, x);
-  int64_t B = g_.n / M, id = 0, mul = 1;
+  const int64_t M = g_.m << l, B = g_.n / M;
+  int64_t id = 0, mul = 1;
   for (int k = 0; k < g_.dim; ++k) {
     id += (x[k] / M) * mul;
     mul *= B;
@@ -69,13 +79,14 @@ int64_t Planner::box_of(int64_t d, int64_t M) const {
 }
 
 // k * B^dim + lexicographic(box indices), with the separator axis k.
-int64_t Planner::group_key(int64_t d, int64_t M) const {
+int64_t Planner::group_key(int64_t d, int l) const {
   int64_t x[3];
   coords(d, x);
-  int64_t B = g_.n / M, id = 0, mul = 1;
+  const int64_t M = g_.m << l, B = g_.n / M;
+  int64_t id = 0, mul = 1;
   int axis = 0;
   for (int k = 0; k < g_.dim; ++k) {
-    if (is_sep(x[k], M)) axis = k;
+    if (seplev_[x[k]] >= l) axis = k;
     id += (x[k] / M) * mul;
     mul *= B;
   }
@@ -94,31 +105,58 @@ void Planner::for_neighbors(int64_t d, F&& f) const {
 
 static inline int64_t link_ref(int64_t N, int64_t lo, int k) { return N * (1 + k) + lo; }
 
+void Planner::drop_inactive() {
+  size_t w = 0;
+  for (size_t i = 0; i < act_.size(); ++i)
+    if (active_[act_[i]]) act_[w++] = act_[i];
+  act_.resize(w);
+}
+
+void Planner::adopt_level0(std::shared_ptr<const LevelPlan> p) {
+  lv_[0].plan = p;
+  lv_[0].res.assign(p->groups.size(), GroupRes{});
+  for (const Cell& C : p->cells)
+    for (int32_t d : C.p) active_[d] = 0;
+  drop_inactive();
+}
+
 // ---------------------------------------------------------------------------
 // Cells of level l
 // ---------------------------------------------------------------------------
 void Planner::plan_cells(int l) {
-  Level& lev = lv_[l];
-  lev.cells.clear();
-  lev.maps.clear();
+  auto lp = std::make_shared<LevelPlan>();
+  build_cells(l, *lp);
+  if (l == 0) building0_ = lp;
+  lv_[l].plan = lp;
+  lv_[l].res.clear();
+  for (const Cell& C : lp->cells)
+    for (int32_t d : C.p) active_[d] = 0;
+  drop_inactive();
+}
+
+void Planner::build_cells(int l, LevelPlan& lp) {
   const bool top = (l == g_.L);
-  const int64_t M = top ? g_.n * 2 : (g_.m << l);  // top: no separators
-  const int64_t B = top ? 1 : g_.n / M;
+  const int64_t B = top ? 1 : g_.n / (g_.m << l);
   int64_t nbox = 1;
   for (int k = 0; k < g_.dim; ++k) nbox *= B;
+  const auto interior = [&](int64_t d) { return top || sigma(d, l) == 0; };
 
-  // Interiors: active unknowns with sigma_l == 0, bucketed by box; the
-  // ascending scan keeps each bucket sorted.
+  // Interiors bucketed by box; the ascending scan keeps buckets sorted.
+  std::vector<int32_t> count(nbox + 1, 0);
+  std::vector<int32_t> dofs;
+  std::vector<int32_t> boxes;
+  for (int32_t d : act_)
+    if (interior(d)) {
+      int64_t b = box_of(d, l);
+      dofs.push_back(d);
+      boxes.push_back(int32_t(b));
+      ++count[b + 1];
+    }
+  for (int64_t b = 0; b < nbox; ++b) count[b + 1] += count[b];
   std::vector<int32_t> cell_of_box(nbox, -1);
-  std::vector<std::vector<int32_t>> bucket(nbox);
-  for (int64_t d = 0; d < g_.N; ++d) {
-    if (!active_[d]) continue;
-    if (!top && sigma(d, M) != 0) continue;
-    bucket[top ? 0 : box_of(d, M)].push_back(int32_t(d));
-  }
   for (int64_t b = 0; b < nbox; ++b) {
-    if (bucket[b].empty()) continue;
-    cell_of_box[b] = int32_t(lev.cells.size());
+    if (count[b + 1] == count[b]) continue;
+    cell_of_box[b] = int32_t(lp.cells.size());
     Cell c;
     c.cid = top ? -1 : b;
     int64_t bb = b, par = 0;
@@ -127,18 +165,18 @@ void Planner::plan_cells(int l) {
       bb /= B;
     }
     c.color = int32_t(par & 1);
-    c.p.swap(bucket[b]);
-    lev.cells.push_back(std::move(c));
+    c.p.reserve(count[b + 1] - count[b]);
+    lp.cells.push_back(std::move(c));
   }
+  for (size_t i = 0; i < dofs.size(); ++i) lp.cells[cell_of_box[boxes[i]]].p.push_back(dofs[i]);
 
-  // Children of each cell (level l-1 cells inside its box).
-  std::vector<std::vector<int32_t>> kids(lev.cells.size());
+  // Children (level l-1 cells inside each box) and interior bases.
+  std::vector<std::vector<int32_t>> kids(lp.cells.size()), gkids(lp.cells.size());
   if (l > 0) {
-    Level& prev = lv_[l - 1];
-    const int64_t Mp = g_.m << (l - 1);
-    const int64_t Bp = g_.n / Mp;
-    for (size_t ci = 0; ci < prev.cells.size(); ++ci) {
-      int64_t pb = prev.cells[ci].cid, parent_box = 0, mul = 1;
+    const Level& prev = lv_[l - 1];
+    const int64_t Bp = g_.n / (g_.m << (l - 1));
+    for (size_t ci = 0; ci < prev.cells().size(); ++ci) {
+      int64_t pb = prev.cells()[ci].cid, parent_box = 0, mul = 1;
       for (int k = 0; k < g_.dim; ++k) {
         int64_t bk = pb % Bp;
         pb /= Bp;
@@ -147,77 +185,58 @@ void Planner::plan_cells(int l) {
       }
       int32_t pc = cell_of_box[parent_box];
       if (pc < 0) throw std::runtime_error("planner: parent box without interior");
-      prev.cells[ci].parent = pc;
       kids[pc].push_back(int32_t(ci));
     }
-  }
-
-  // Groups of level l-1/2 whose survivors are interior here feed the cells.
-  std::vector<std::vector<int32_t>> gkids(lev.cells.size());
-  if (l > 0) {
-    Level& prev = lv_[l - 1];
-    for (size_t gi = 0; gi < prev.groups.size(); ++gi) {
-      const Group& G = prev.groups[gi];
-      const auto& surv = G.skel ? G.sk : G.c;
+    for (size_t gi = 0; gi < prev.groups().size(); ++gi) {
+      const auto& surv = prev.survivors(gi);
       if (surv.empty()) continue;
       int64_t d0 = surv[0];
-      if (!top && sigma(d0, M) != 0) continue;
-      gkids[cell_of_box[top ? 0 : box_of(d0, M)]].push_back(int32_t(gi));
+      if (!interior(d0)) continue;
+      gkids[cell_of_box[box_of(d0, l)]].push_back(int32_t(gi));
     }
   }
 
-  for (size_t ci = 0; ci < lev.cells.size(); ++ci) {
-    Cell& C = lev.cells[ci];
-    // Front q^+: surviving fronts of the children that are not interior here,
-    // plus active stencil neighbours of the interior.
+  for (size_t ci = 0; ci < lp.cells.size(); ++ci) {
+    Cell& C = lp.cells[ci];
+    // Front q^+: surviving fronts of the children that are not interior
+    // here, plus active stencil neighbours of the interior.
     std::vector<int32_t> q;
-    if (l > 0) {
+    if (l > 0)
       for (int32_t k : kids[ci])
-        for (int32_t z : lv_[l - 1].cells[k].q)
-          if (active_[z] && (top ? false : sigma(z, M) != 0)) q.push_back(z);
-    }
+        for (int32_t z : lv_[l - 1].cells()[k].q)
+          if (active_[z] && !interior(z)) q.push_back(z);
     for (int32_t d : C.p)
       for_neighbors(d, [&](int64_t z, int, bool) {
-        if (active_[z] && (top ? false : sigma(z, M) != 0)) q.push_back(int32_t(z));
+        if (active_[z] && !interior(z)) q.push_back(int32_t(z));
       });
     std::sort(q.begin(), q.end());
     q.erase(std::unique(q.begin(), q.end()), q.end());
     C.q.swap(q);
 
-    // Local numbering [p; q].
     const int32_t np = int32_t(C.p.size());
     for (int32_t i = 0; i < np; ++i) loc_[C.p[i]] = i;
     for (int32_t i = 0; i < int32_t(C.q.size()); ++i) loc_[C.q[i]] = np + i;
 
     if (l > 0) {
-      Level& prev = lv_[l - 1];
+      const Level& prev = lv_[l - 1];
       for (int32_t k : kids[ci]) {
-        const Cell& K = prev.cells[k];
-        Source s;
-        s.kind = SRC_CELL_U;
-        s.level = l - 1;
-        s.index = k;
-        s.dim = int32_t(K.q.size());
-        s.rowmap = s.colmap = int64_t(lev.maps.size());
+        const Cell& K = prev.cells()[k];
+        Source s{SRC_CELL_U, l - 1, k, int32_t(K.q.size()), int64_t(lp.maps.size()), 0};
+        s.colmap = s.rowmap;
         for (int32_t z : K.q) {
           if (active_[z] && loc_[z] < 0)
             throw std::runtime_error("planner: child front unknown lost by its parent");
-          lev.maps.push_back(active_[z] ? loc_[z] : -1);
+          lp.maps.push_back(active_[z] ? loc_[z] : -1);
         }
         C.src.push_back(s);
       }
       for (int32_t gi : gkids[ci]) {
-        const Group& G = prev.groups[gi];
-        const auto& surv = G.skel ? G.sk : G.c;
-        Source s;
-        s.kind = SRC_GROUP_BASE;
-        s.level = l - 1;
-        s.index = gi;
-        s.dim = int32_t(surv.size());
-        s.rowmap = s.colmap = int64_t(lev.maps.size());
+        const auto& surv = prev.survivors(gi);
+        Source s{SRC_GROUP_BASE, l - 1, gi, int32_t(surv.size()), int64_t(lp.maps.size()), 0};
+        s.colmap = s.rowmap;
         for (int32_t z : surv) {
           if (loc_[z] < 0) throw std::runtime_error("planner: base unknown outside its cell");
-          lev.maps.push_back(loc_[z]);
+          lp.maps.push_back(loc_[z]);
         }
         C.src.push_back(s);
       }
@@ -230,85 +249,93 @@ void Planner::plan_cells(int l) {
         if (loc_[z] < 0) throw std::runtime_error("planner: active neighbour outside the front");
         if (grouped_[d] && grouped_[z]) return;
         if (loc_[z] < np && z < d) return;  // interior pair: once
-        int64_t lo = up ? d : z;
-        C.trips.push_back({loc_[d], loc_[z], link_ref(g_.N, lo, k)});
+        C.trips.push_back({loc_[d], loc_[z], link_ref(g_.N, up ? d : z, k)});
       });
     }
     for (int32_t d : C.p) loc_[d] = -1;
     for (int32_t d : C.q) loc_[d] = -1;
   }
-  // Eliminated unknowns leave the active set.
-  for (const Cell& C : lev.cells)
-    for (int32_t d : C.p) active_[d] = 0;
-  if (top) top_done_ = true;
 }
 
 // ---------------------------------------------------------------------------
 // Groups of level l+1/2
 // ---------------------------------------------------------------------------
-void Planner::plan_groups(int l, bool skeletonize) {
-  Level& lev = lv_[l];
-  lev.groups.clear();
-  const int64_t M = g_.m << l;
-  (void)skeletonize;
-
-  std::vector<std::pair<int64_t, int32_t>> keyed;
-  for (int64_t d = 0; d < g_.N; ++d)
-    if (active_[d] && sigma(d, M) == 1) keyed.push_back({group_key(d, M), int32_t(d)});
-  std::sort(keyed.begin(), keyed.end());
-  std::vector<int32_t> group_of(0);
-  for (size_t i = 0; i < keyed.size();) {
-    size_t j = i;
-    Group G;
-    G.gid = keyed[i].first;
-    while (j < keyed.size() && keyed[j].first == keyed[i].first) G.c.push_back(keyed[j++].second);
-    lev.groups.push_back(std::move(G));
-    i = j;
+void Planner::plan_groups(int l) {
+  // The level's cells were planned by plan_cells(l) into a plan this planner
+  // created (level 0 too, unless it was adopted; adopted plans already hold
+  // their groups).
+  std::shared_ptr<LevelPlan> lp = std::const_pointer_cast<LevelPlan>(lv_[l].plan);
+  if (l == 0 && !building0_) {
+    lv_[0].res.assign(lp->groups.size(), GroupRes{});
+    return;
   }
-  // Which level-l fronts hold each unknown (at most a few).
-  std::vector<int32_t> own0(g_.N, -1), own1(g_.N, -1);
-  for (size_t ci = 0; ci < lev.cells.size(); ++ci)
-    for (int32_t z : lev.cells[ci].q) {
-      if (own0[z] < 0) own0[z] = int32_t(ci);
-      else if (own1[z] < 0) own1[z] = int32_t(ci);
+  lp->groups.clear();
+  lp->gmaps.clear();
+  build_groups(l, *lp);
+  lv_[l].res.assign(lp->groups.size(), GroupRes{});
+  if (l == 0) building0_.reset();
+}
+
+void Planner::build_groups(int l, LevelPlan& lp) {
+  const int64_t B = g_.n / (g_.m << l);
+  int64_t nkey = g_.dim;
+  for (int k = 0; k < g_.dim; ++k) nkey *= B;
+  std::vector<int32_t> count(nkey + 1, 0), keys;
+  std::vector<int32_t> dofs;
+  for (int32_t d : act_)
+    if (sigma(d, l) == 1) {
+      int64_t key = group_key(d, l);
+      dofs.push_back(d);
+      keys.push_back(int32_t(key));
+      ++count[key + 1];
+    }
+  for (int64_t b = 0; b < nkey; ++b) count[b + 1] += count[b];
+  std::vector<int32_t> group_of_key(nkey, -1);
+  for (int64_t b = 0; b < nkey; ++b) {
+    if (count[b + 1] == count[b]) continue;
+    group_of_key[b] = int32_t(lp.groups.size());
+    Group G;
+    G.gid = b;
+    G.c.reserve(count[b + 1] - count[b]);
+    lp.groups.push_back(std::move(G));
+  }
+  for (size_t i = 0; i < dofs.size(); ++i) lp.groups[group_of_key[keys[i]]].c.push_back(dofs[i]);
+
+  // Which level-l fronts hold each unknown (at most two).
+  const auto& cells = lp.cells;
+  for (size_t ci = 0; ci < cells.size(); ++ci)
+    for (int32_t z : cells[ci].q) {
+      if (own0_[z] < 0) own0_[z] = int32_t(ci);
+      else if (own1_[z] < 0) own1_[z] = int32_t(ci);
       else throw std::runtime_error("planner: unknown in more than two fronts");
     }
   // Earlier bases that land in each group.
-  std::vector<int64_t> gkey_index;
-  std::vector<std::vector<int32_t>> gkids(lev.groups.size());
+  std::vector<std::vector<int32_t>> gkids(lp.groups.size());
   if (l > 0) {
     const Level& prev = lv_[l - 1];
-    // map key -> group index
-    for (size_t gi = 0; gi < prev.groups.size(); ++gi) {
-      const Group& P = prev.groups[gi];
-      const auto& surv = P.skel ? P.sk : P.c;
+    for (size_t gi = 0; gi < prev.groups().size(); ++gi) {
+      const auto& surv = prev.survivors(gi);
       if (surv.empty()) continue;
       int32_t d0 = surv[0];
-      if (sigma(d0, M) != 1) continue;
-      int64_t key = group_key(d0, M);
-      auto it = std::lower_bound(lev.groups.begin(), lev.groups.end(), key,
-                                 [](const Group& a, int64_t k) { return a.gid < k; });
-      if (it == lev.groups.end() || it->gid != key)
-        throw std::runtime_error("planner: base without group");
-      gkids[it - lev.groups.begin()].push_back(int32_t(gi));
+      if (sigma(d0, l) != 1) continue;
+      int32_t g = group_of_key[group_key(d0, l)];
+      if (g < 0) throw std::runtime_error("planner: base without group");
+      gkids[g].push_back(int32_t(gi));
     }
   }
-  std::vector<uint8_t> in_g(0);
-  for (size_t gi = 0; gi < lev.groups.size(); ++gi) {
-    Group& G = lev.groups[gi];
+  for (size_t gi = 0; gi < lp.groups.size(); ++gi) {
+    Group& G = lp.groups[gi];
     const int32_t nc = int32_t(G.c.size());
-    // Neighbour set: the other unknowns of the adjacent fronts and the
-    // active stencil neighbours outside c.
-    for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = i;  // mark c
-    std::vector<int32_t> cells, cn;
+    for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = i;
+    std::vector<int32_t> adj, cn;
     for (int32_t d : G.c) {
-      if (own0[d] >= 0) cells.push_back(own0[d]);
-      if (own1[d] >= 0) cells.push_back(own1[d]);
+      if (own0_[d] >= 0) adj.push_back(own0_[d]);
+      if (own1_[d] >= 0) adj.push_back(own1_[d]);
     }
-    std::sort(cells.begin(), cells.end());
-    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
-    for (int32_t ci : cells)
-      for (int32_t z : lev.cells[ci].q)
+    std::sort(adj.begin(), adj.end());
+    adj.erase(std::unique(adj.begin(), adj.end()), adj.end());
+    for (int32_t ci : adj)
+      for (int32_t z : cells[ci].q)
         if (loc_[z] < 0) cn.push_back(z);
     for (int32_t d : G.c)
       for_neighbors(d, [&](int64_t z, int, bool) {
@@ -317,26 +344,18 @@ void Planner::plan_groups(int l, bool skeletonize) {
     std::sort(cn.begin(), cn.end());
     cn.erase(std::unique(cn.begin(), cn.end()), cn.end());
     G.cN.swap(cn);
-    // Rows [c^N; c]: local index of row unknowns; columns: c.
     const int32_t nn = int32_t(G.cN.size());
-    for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = -1;
 
-    // Base formation sources (column side == row side, local in c).
-    for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = i;
+    // Base formation: earlier bases and loose entries inside c (local in c).
     if (l > 0) {
       const Level& prev = lv_[l - 1];
       for (int32_t pg : gkids[gi]) {
-        const Group& P = prev.groups[pg];
-        const auto& surv = P.skel ? P.sk : P.c;
-        Source s;
-        s.kind = SRC_GROUP_BASE;
-        s.level = l - 1;
-        s.index = pg;
-        s.dim = int32_t(surv.size());
-        s.rowmap = s.colmap = int64_t(lev.maps.size());
+        const auto& surv = prev.survivors(pg);
+        Source s{SRC_GROUP_BASE, l - 1, pg, int32_t(surv.size()), int64_t(lp.gmaps.size()), 0};
+        s.colmap = s.rowmap;
         for (int32_t z : surv) {
           if (loc_[z] < 0) throw std::runtime_error("planner: base unknown outside its group");
-          lev.maps.push_back(loc_[z]);
+          lp.gmaps.push_back(loc_[z]);
         }
         G.bsrc.push_back(s);
       }
@@ -357,68 +376,54 @@ void Planner::plan_groups(int l, bool skeletonize) {
         auto it = std::lower_bound(G.cN.begin(), G.cN.end(), int32_t(z));
         if (it == G.cN.end() || *it != int32_t(z))
           throw std::runtime_error("planner: stencil neighbour missing from c^N");
-        int32_t row = int32_t(it - G.cN.begin());
-        G.gtrips.push_back({row, loc_[d], link_ref(g_.N, up ? d : z, k)});
+        G.gtrips.push_back({int32_t(it - G.cN.begin()), loc_[d], link_ref(g_.N, up ? d : z, k)});
       });
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = -1;
 
     // Cell update blocks -> [c^N; c] x c.
     for (int32_t i = 0; i < nn; ++i) loc_[G.cN[i]] = i;
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = nn + i;
-    for (int32_t ci : cells) {
-      const Cell& C = lev.cells[ci];
-      Source s;
-      s.kind = SRC_CELL_U;
-      s.level = l;
-      s.index = ci;
-      s.dim = int32_t(C.q.size());
-      s.rowmap = int64_t(lev.maps.size());
-      for (int32_t z : C.q) lev.maps.push_back(loc_[z]);
-      s.colmap = int64_t(lev.maps.size());
-      for (int32_t z : C.q) lev.maps.push_back(loc_[z] >= nn ? loc_[z] - nn : -1);
+    for (int32_t ci : adj) {
+      const Cell& C = cells[ci];
+      Source s{SRC_CELL_U, l, ci, int32_t(C.q.size()), int64_t(lp.gmaps.size()), 0};
+      for (int32_t z : C.q) lp.gmaps.push_back(loc_[z]);
+      s.colmap = int64_t(lp.gmaps.size());
+      for (int32_t z : C.q) lp.gmaps.push_back(loc_[z] >= nn ? loc_[z] - nn : -1);
       G.gsrc.push_back(s);
     }
     for (int32_t i = 0; i < nn; ++i) loc_[G.cN[i]] = -1;
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = -1;
-    G.skel = false;
-    G.k = nc;
   }
+  for (const Cell& C : cells)
+    for (int32_t z : C.q) own0_[z] = own1_[z] = -1;
 }
 
 void Planner::set_skeleton(int l, int gi, int k, const int32_t* sk_pos) {
-  Group& G = lv_[l].groups.at(gi);
+  const Group& G = lv_[l].plan->groups.at(gi);
+  GroupRes& R = lv_[l].res.at(gi);
   const int32_t nc = int32_t(G.c.size());
-  G.k = k;
-  G.sk.clear();
-  G.rd.clear();
-  G.sk_loc.clear();
-  G.rd_loc.clear();
+  R.k = k;
+  R.sk.clear();
+  R.rd.clear();
   if (k >= nc) {
-    G.skel = false;
+    R.skel = false;
+    R.k = nc;
     return;
   }
-  G.skel = true;
+  R.skel = true;
   std::vector<uint8_t> is_sk(nc, 0);
   for (int i = 0; i < k; ++i) is_sk.at(sk_pos[i]) = 1;
-  for (int32_t i = 0; i < nc; ++i) {
-    if (is_sk[i]) {
-      G.sk.push_back(G.c[i]);
-      G.sk_loc.push_back(i);
-    } else {
-      G.rd.push_back(G.c[i]);
-      G.rd_loc.push_back(i);
-    }
-  }
+  for (int32_t i = 0; i < nc; ++i) (is_sk[i] ? R.sk : R.rd).push_back(G.c[i]);
 }
 
 void Planner::finish_groups(int l) {
-  Level& lev = lv_[l];
-  for (Group& G : lev.groups) {
-    for (int32_t d : G.c) grouped_[d] = 1;
-    if (G.skel)
-      for (int32_t d : G.rd) active_[d] = 0;
+  const Level& lev = lv_[l];
+  for (size_t gi = 0; gi < lev.groups().size(); ++gi) {
+    for (int32_t d : lev.groups()[gi].c) grouped_[d] = 1;
+    if (lev.res[gi].skel)
+      for (int32_t d : lev.res[gi].rd) active_[d] = 0;
   }
-  lev.groups_done = true;
+  drop_inactive();
 }
 
 }  // namespace hifde

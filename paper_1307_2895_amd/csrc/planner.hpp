@@ -16,9 +16,14 @@
 //     anything else are "loose": they are read from the stencil when the cell
 //     or group that first contains both ends is formed.
 // So at level l+1/2, A_{l+1/2}[i,j] = sum_C U_C[i,j] + sum_G E_G[i,j] + loose.
+//
+// The level-0 cells and the level-1/2 groups depend on the geometry only; a
+// tree builds them once (LevelPlan, immutable, shared) and every
+// factorization of that tree reuses them.
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -39,9 +44,8 @@ struct Trip {
   int64_t ref;
 };
 
-// Where an assembly source lives; resolved to a device pointer by the caller.
 enum SrcKind : int32_t {
-  SRC_CELL_U = 0,   // trailing (update) block of a cell's frontal matrix
+  SRC_CELL_U = 0,     // trailing (update) block of a cell's frontal matrix
   SRC_GROUP_BASE = 1  // base block of a group
 };
 
@@ -60,7 +64,6 @@ struct Cell {
   std::vector<int32_t> p, q;         // eliminated unknowns, front (sorted)
   std::vector<Source> src;           // extend-add sources
   std::vector<Trip> trips;           // loose stencil entries (local indices)
-  int64_t parent = -1;               // index of the parent cell at level l+1
 };
 
 struct Group {
@@ -70,57 +73,76 @@ struct Group {
   std::vector<Trip> btrips;          // base formation: loose entries in c
   std::vector<Source> gsrc;          // [c^N; c] x c block: cell update blocks
   std::vector<Trip> gtrips;          // loose links (row in [c^N; c], col in c)
-  bool skel = false;                 // skeletonized (0 <= k < |c|)
+};
+
+// Skeleton choice of a group (value dependent).
+struct GroupRes {
+  bool skel = false;                 // skeletonized (k < |c|)
   int32_t k = 0;
   std::vector<int32_t> sk, rd;       // skeletons / redundant (sorted, global)
-  std::vector<int32_t> sk_loc, rd_loc; // same, as positions in c
+};
+
+// Structure of one level: cells of level l and groups of level l+1/2.
+struct LevelPlan {
+  std::vector<Cell> cells;
+  std::vector<Group> groups;
+  std::vector<int32_t> maps;         // maps of the cells' sources
+  std::vector<int32_t> gmaps;        // maps of the groups' sources
 };
 
 struct Level {
-  std::vector<Cell> cells;
-  std::vector<Group> groups;
-  std::vector<int32_t> maps;         // all maps of this level's sources
-  bool groups_done = false;
+  std::shared_ptr<const LevelPlan> plan;
+  std::vector<GroupRes> res;
+  const std::vector<Cell>& cells() const { return plan->cells; }
+  const std::vector<Group>& groups() const { return plan->groups; }
+  const std::vector<int32_t>& survivors(size_t gi) const {
+    return res[gi].skel ? res[gi].sk : plan->groups[gi].c;
+  }
 };
 
 class Planner {
  public:
-  Planner(const Geom& g);
+  explicit Planner(const Geom& g);
 
   const Geom& geom() const { return g_; }
-  // Level l cells (l = L gives the top block).  Requires groups of l-1/2
-  // to have their skeletons applied.
+  // Level l cells (l = L gives the top block).  Requires the groups of
+  // l-1/2 to be finished.
   void plan_cells(int l);
-  // Level l+1/2 groups; requires cells of level l planned (their interiors
-  // are removed from the active set here).
-  void plan_groups(int l, bool skeletonize);
-  // Record the skeleton choice of group gi of level l+1/2: k skeletons at the
-  // given positions of c (sorted ascending).  k == |c| leaves it alone.
+  // Level l+1/2 groups; requires the cells of level l planned.
+  void plan_groups(int l);
+  // Record the skeleton choice of group gi of level l+1/2: k skeletons at
+  // the given positions of c (sorted ascending).  k >= |c| leaves it alone.
   void set_skeleton(int l, int gi, int k, const int32_t* sk_pos);
   // Finish level l+1/2 after every set_skeleton call.
   void finish_groups(int l);
 
-  std::vector<Level>& levels() { return lv_; }
+  // The structure of level 0 (cells and groups) as planned so far, to be
+  // shared with later factorizations of the same tree.
+  std::shared_ptr<const LevelPlan> level0() const { return lv_.at(0).plan; }
+  // Start a factorization from a previously planned level 0.
+  void adopt_level0(std::shared_ptr<const LevelPlan> p);
+
   const std::vector<Level>& levels() const { return lv_; }
-  const Cell& top() const { return lv_.back().cells.at(0); }
-  bool has_top() const { return top_done_; }
-  int64_t active_count() const;
+  const Level& level(int l) const { return lv_.at(l); }
 
  private:
-  int sigma(int64_t d, int64_t M) const;
+  int sigma(int64_t d, int l) const;
   void coords(int64_t d, int64_t* x) const;
-  bool is_sep(int64_t x, int64_t M) const {
-    return ((x + 1) % M == 0) && (x != g_.n - 1);
-  }
-  int64_t box_of(int64_t d, int64_t M) const;
-  int64_t group_key(int64_t d, int64_t M) const;
+  int64_t box_of(int64_t d, int l) const;
+  int64_t group_key(int64_t d, int l) const;
   template <class F> void for_neighbors(int64_t d, F&& f) const;
+  void build_cells(int l, LevelPlan& lp);
+  void build_groups(int l, LevelPlan& lp);
+  void drop_inactive();
 
   Geom g_;
+  std::vector<int8_t> seplev_;       // highest level at which x is a separator
   std::vector<uint8_t> active_, grouped_;
-  std::vector<int32_t> loc_;          // scratch: global -> local (-1)
+  std::vector<int32_t> act_;         // sorted active unknowns
+  std::vector<int32_t> loc_;         // scratch: global -> local (-1)
+  std::vector<int32_t> own0_, own1_; // scratch: fronts holding an unknown
   std::vector<Level> lv_;
-  bool top_done_ = false;
+  std::shared_ptr<LevelPlan> building0_;
 };
 
 // Validates a tree request; returns an empty string when valid.
