@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -214,6 +215,19 @@ namespace hifde {
 
 static inline unsigned nblk(int64_t n, int t = kThreads) { return unsigned((n + t - 1) / t); }
 
+// Host-side phase timer, printed to stderr when HIFDE_TIMING is set.
+struct PhaseTimer {
+  bool on = getenv("HIFDE_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what, int l) {
+    if (!on) return;
+    auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "[hifde] level %d %-18s %8.3f ms\n", l, what,
+            std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Source resolution: pool and element offset of a planned block.
 // ---------------------------------------------------------------------------
@@ -282,7 +296,6 @@ static void upload_cell_static(CellStatic& cs, hipStream_t st) {
   cs.maps = cs.mem.upload(*cs.maps_h, st);
   cs.trips = cs.mem.upload(cs.trips_h, st);
   cs.idx = cs.mem.upload(cs.idx_h, st);
-  HIP_CHECK(hipStreamSynchronize(st));
   cs.on_device = true;
 }
 
@@ -337,7 +350,6 @@ static void upload_group_static(GroupStatic& gs, hipStream_t st) {
   gs.btrips = gs.mem.upload(gs.btrips_h, st);
   gs.gsrcs = gs.mem.upload(gs.gsrcs_h, st);
   gs.gtrips = gs.mem.upload(gs.gtrips_h, st);
-  HIP_CHECK(hipStreamSynchronize(st));
   gs.on_device = true;
 }
 
@@ -449,11 +461,14 @@ template <typename T, typename TS>
 static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
   CellLevel& D = F.cl[l];
+  PhaseTimer tm;
   if (l == 0 && tree->c0) {
     D.st = tree->c0;
   } else {
     if (l > 0) P.plan_cells(l);
+    tm.mark("  plan cells", l);
     D.st = make_cell_static(F, *P.level(l).plan);
+    tm.mark("  cell descriptors", l);
     if (l == 0) {
       tree->c0 = D.st;
       tree->c0_esz = sizeof(T);
@@ -499,13 +514,16 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   Planner& P = *F.planner;
   const bool skel = F.eps > 0.0 && l >= F.g.skip;
   GroupLevel& G = F.gl[l];
+  PhaseTimer tm;
   P.plan_groups(l);
+  tm.mark("  plan groups", l);
   if (l == 0 && tree->g0 && (tree->g0->gw_elems > 0) == skel) {
     G.st = tree->g0;
   } else {
     G.st = make_group_static(F, *P.level(l).plan, skel);
     if (l == 0) tree->g0 = G.st;
   }
+  tm.mark("  group descriptors", l);
   GroupStatic& S = *G.st;
   G.gh = S.gh;
   G.ngroup = int(G.gh.size());
@@ -552,7 +570,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
   HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
+  PhaseTimer tw;
   HIP_CHECK(hipStreamSynchronize(st));
+  tw.mark("  wait for IDs", l);
   // record skeletons; build the skeleton fronts
   int64_t fg_off = 0;
   G.gsel_h.clear();
@@ -582,6 +602,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     G.ncskel = std::max(G.ncskel, int(d.nc));
   }
   P.finish_groups(l);
+  tm.mark("  skeletons", l);
   G.nskel = int(G.gsel_h.size());
   G.groups = F.mem.upload(G.gh, st);
   if (G.nskel == 0) return;
@@ -606,6 +627,7 @@ template <typename T>
 static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   const int L = F.g.L;
   Planner& P = *F.planner;
+  PhaseTimer tm;
   // Level 0 and its groups depend on the geometry only: plan once per tree.
   if (!tree->l0) {
     P.plan_cells(0);
@@ -616,15 +638,22 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   } else {
     P.adopt_level0(tree->l0);
   }
+  tm.mark("level-0 plan", 0);
   for (int l = 0; l < L; ++l) {
     cells_level<T, T>(F, tree, l, st);
-    if (!F.plan_only) check_info(F.cl[l].info, F.cl[l].st->fh.size(), "cell", l, st);
+    tm.mark("cells", l);
     groups_level<T>(F, tree, l, st);
-    if (!F.plan_only && F.gl[l].nskel > 0)
-      check_info(F.gl[l].info, size_t(F.gl[l].nskel), "group", l, st);
+    tm.mark("groups", l);
   }
   cells_level<double, T>(F, tree, L, st);
-  if (!F.plan_only) check_info(F.cl[L].info, F.cl[L].st->fh.size(), "top block", L, st);
+  tm.mark("top", L);
+  if (F.plan_only) return;
+  // pivot checks of every level at once (one synchronization)
+  for (int l = 0; l <= L; ++l) {
+    check_info(F.cl[l].info, F.cl[l].st->fh.size(), l == L ? "top block" : "cell", l, st);
+    if (l < L && F.gl[l].nskel > 0) check_info(F.gl[l].info, size_t(F.gl[l].nskel), "group", l, st);
+  }
+  tm.mark("pivot checks", L);
 }
 
 static void fill_stats(hifde_factor_s& F) {
@@ -831,9 +860,12 @@ int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level, hifde_f
     F->plan_only = true;
     F->planner.reset(new Planner(F->g));
     Planner& P = *F->planner;
+    PhaseTimer tm;
     for (int l = 0; l < F->g.L; ++l) {
       P.plan_cells(l);
+      tm.mark("plan cells", l);
       P.plan_groups(l);
+      tm.mark("plan groups", l);
       const auto& groups = P.level(l).groups();
       for (size_t gi = 0; gi < groups.size(); ++gi) {
         std::vector<int32_t> sk;
