@@ -29,6 +29,12 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
+# The kernel the roofline object describes: the upward cell sweep of F^-1
+# (every launch of k_cell_up<float, float>, all levels and both colors).
+DOMINANT_KERNEL = "k_cell_up<float, float>"
+DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
+CALIB_COPY_BYTES = 512 << 20
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -39,7 +45,95 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path")
     ap.add_argument("--cpu-n", type=int, default=256, help="grid side of the CPU oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help=f"first run one plain device copy of {CALIB_COPY_BYTES >> 20} MiB "
+                         "(scale reference for HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this script with --calib-copy and exit")
     return ap.parse_args()
+
+
+def source_sha(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_file(workload):
+    name = DOMINANT_KERNEL.split("<")[0]
+    return os.path.join(ROOT, "profiles", f"traffic_{name}_{workload}.txt")
+
+
+def read_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when absent or taken on a different kernel source."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != source_sha(DOMINANT_SOURCE):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, grid size, value) rows of a rocprofv3 counter CSV."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0),
+                                 float(r["Counter_Value"])))
+    return rows
+
+
+def pmc_summary(fetch_dir, write_dir, workload):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the dominant kernel,
+    scaled by what the same counters read for the calibration copy."""
+    out = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _pmc_rows(d, counter)
+        # per dispatch: the counter is reported per dispatch (summed over instances)
+        copy = [v for n, g, v in rows if "copy" in n.lower()]
+        dom = [v for n, g, v in rows if DOMINANT_KERNEL.replace(" ", "") in n.replace(" ", "")]
+        if not copy or not dom:
+            raise SystemExit(f"{counter}: calibration copy or {DOMINANT_KERNEL} not found in {d}")
+        copy_kib = max(copy)
+        scale = (CALIB_COPY_BYTES / 1024.0) / copy_kib
+        out[key] = (len(dom), float(np.mean(dom)), scale)
+    nd, fkib, fs = out["fetch"]
+    _, wkib, ws = out["write"]
+    traffic = (fkib * fs + wkib * ws) * 1024.0
+    lines = [
+        f"# HBM traffic of {DOMINANT_KERNEL} on {workload} from rocprofv3 counters",
+        "# commands (from the repository root, TMPDIR=/tmp):",
+        f"#   rocprofv3 --pmc FETCH_SIZE -f csv -d <FETCH_DIR> -- python bench.py --steps 1 "
+        f"--warmup 0 --no-cpu --no-fp64 --calib-copy",
+        f"#   rocprofv3 --pmc WRITE_SIZE -f csv -d <WRITE_DIR> -- python bench.py --steps 1 "
+        f"--warmup 0 --no-cpu --no-fp64 --calib-copy",
+        f"#   python bench.py --pmc-summary <FETCH_DIR> <WRITE_DIR>",
+        f"kernel: {DOMINANT_KERNEL}",
+        f"kernel_source_sha256: {source_sha(DOMINANT_SOURCE)}",
+        f"dispatches: {nd}",
+        f"fetch_kib_per_dispatch: {fkib:.1f}",
+        f"write_kib_per_dispatch: {wkib:.1f}",
+        f"copy_fetch_scale: {fs:.4f}",
+        f"copy_write_scale: {ws:.4f}",
+        f"traffic_bytes_per_launch: {traffic:.0f}",
+    ]
+    return "\n".join(lines)
 
 
 def cpu_baseline(w, n_sample, nrhs):
@@ -73,6 +167,9 @@ def cpu_baseline(w, n_sample, nrhs):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
               "the method's multi-GPU sharding is described in DESIGN.md and not built.",
@@ -92,15 +189,30 @@ def main():
     tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
     prec = H.HIFDE_MIXED if w.precision == "mixed" else H.HIFDE_FP64
 
-    def step(p):
+    if args.calib_copy:
+        src = torch.ones(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    prof = {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0}
+
+    def step(p, profile=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = H.hifde_factor(tree, a_d, None, w.eps, p)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if profile:
+            H.hifde_profile(F, 1 << H.HIFDE_PROF_CELL_UP, -1)
         u, its, rel = H.hifde_pcg(F, f_d, tol=1e-12, maxit=200)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        if profile:
+            r = H.hifde_profile_read(F, H.HIFDE_PROF_CELL_UP)
+            for k in prof:
+                prof[k] += r[k]
         st = H.hifde_stats(F)
         F.free()
         return t1 - t0, t2 - t1, its, rel, st
@@ -112,7 +224,7 @@ def main():
     tf, tp, iters = [], [], None
     t_begin = time.perf_counter()
     for k in range(args.steps):
-        a, b, its, rel, st = step(prec)
+        a, b, its, rel, st = step(prec, profile=True)
         tf.append(a)
         tp.append(b)
         iters, relres, stats = its, rel, st
@@ -149,6 +261,18 @@ def main():
             "factor_bytes": stats["factor_bytes"],
             "factor_gflop": stats["factor_flops"] / 1e9,
         },
+    }
+    nl = max(1, prof["launches"])
+    avg_s = prof["ms"] / nl / 1e3
+    bytes_launch = prof["bytes"] / nl
+    achieved = bytes_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = read_traffic(w.name)
+    out["roofline"] = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "kernel": DOMINANT_KERNEL, "launches": prof["launches"],
+        "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
+        "mfma_tflops": prof["flops"] / nl / avg_s / 1e12 if avg_s > 0 else 0.0,
     }
     if not args.no_fp64 and prec == H.HIFDE_MIXED:
         a, b, its, rel, st = step(H.HIFDE_FP64)

@@ -140,6 +140,39 @@ int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
 int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
                  double* y, int64_t ldy, void* hip_stream);
 
+/* Kernel timing.  Launches of the selected kernel classes are bracketed by
+ * HIP events on the stream they run on; hifde_profile_read reports, per
+ * class, the launches timed, their summed event time and their algorithmic
+ * traffic and flops (the bytes of the stored factor blocks, index lists and
+ * vector rows the launch must touch, and the multiply-adds the sweep
+ * formulas of Section 4.1 need), so that achieved bandwidth can be compared
+ * with the device's.  Profiling adds two event records per timed launch. */
+enum {
+  HIFDE_PROF_CELL_UP = 0,     /* upward cell step: x_p <- D^-1 L^-1 x_p,
+                                 x_q -= W^T L^-1 x_p (Lemma 2.1)            */
+  HIFDE_PROF_CELL_DOWN = 1,   /* downward cell step: x_p <- L^-T (x_p - W x_q) */
+  HIFDE_PROF_GROUP_UP = 2,    /* upward group step (Lemma 2.4)              */
+  HIFDE_PROF_GROUP_DOWN = 3,  /* downward group step                        */
+  HIFDE_PROF_TOP = 4,         /* both steps of the top block (double)       */
+  HIFDE_PROF_CLASSES = 5
+};
+
+typedef struct {
+  int64_t launches;   /* launches timed since the last read                   */
+  double ms;          /* summed HIP-event durations                          */
+  double bytes;       /* algorithmic bytes of those launches                 */
+  double flops;       /* algorithmic flops of those launches                 */
+} hifde_prof_t;
+
+/* Start timing the classes in class_mask (bit c = class c) at tree level
+ * `level` (-1: every level); class_mask = 0 stops.  Counters are kept until
+ * read. */
+int hifde_profile(hifde_factor_t F, uint32_t class_mask, int level);
+
+/* Waits for the timed launches of class cls, adds them up into *out (HOST)
+ * and clears the class's counters. */
+int hifde_profile_read(hifde_factor_t F, int cls, hifde_prof_t* out);
+
 /* Statistics of a factor (HOST out). */
 int hifde_stats(hifde_factor_t F, hifde_stats_t* out);
 

@@ -12,8 +12,10 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (  # noqa: F401
-    HIFDE_FP64, HIFDE_MIXED, HifdeError, Sets, Stats, check, lib,
+    HIFDE_FP64, HIFDE_MIXED, HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
+    HIFDE_PROF_CELL_UP, HIFDE_PROF_CELL_DOWN, HIFDE_PROF_GROUP_UP, HIFDE_PROF_GROUP_DOWN,
+    HIFDE_PROF_TOP, HIFDE_PROF_CLASSES,
 )
 
 
@@ -24,9 +26,12 @@ class Tree:
         self.N = n ** dim
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().hifde_tree_free(self._h)
-            self._h = None
+        try:
+            if getattr(self, "_h", None):
+                lib().hifde_tree_free(self._h)
+                self._h = None
+        except Exception:  # interpreter shutdown: the library may be gone
+            pass
 
 
 class Factor:
@@ -45,7 +50,10 @@ class Factor:
             self._h = None
 
     def __del__(self):
-        self.free()
+        try:
+            self.free()
+        except Exception:  # interpreter shutdown: the library may be gone
+            pass
 
 
 def _stream(stream):
@@ -141,6 +149,20 @@ def hifde_stats(F: Factor) -> dict:
         "skel_in": list(s.skel_in[:L]), "skel_out": list(s.skel_out[:L]),
         "max_front": list(s.max_front[:L + 1]),
     }
+
+
+def hifde_profile(F: Factor, class_mask: int, level: int = -1):
+    """Time the launches of the kernel classes in ``class_mask`` at tree
+    level ``level`` (-1: all) with HIP events; 0 stops."""
+    check(lib().hifde_profile(F._h, int(class_mask), int(level)))
+
+
+def hifde_profile_read(F: Factor, cls: int) -> dict:
+    """Launches, summed event milliseconds and algorithmic bytes/flops of
+    class ``cls`` since the last read."""
+    p = Prof()
+    check(lib().hifde_profile_read(F._h, int(cls), C.byref(p)))
+    return {"launches": p.launches, "ms": p.ms, "bytes": p.bytes, "flops": p.flops}
 
 
 def hifde_export_sets(F: Factor, level2: int):

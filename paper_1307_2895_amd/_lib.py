@@ -25,9 +25,13 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD
 
 EXPORTED = [
     "hifde_build_tree", "hifde_factor", "hifde_solve", "hifde_pcg", "hifde_matvec",
-    "hifde_stats", "hifde_export_sets", "hifde_plan_replay", "hifde_tree_free",
-    "hifde_factor_free", "hifde_last_error",
+    "hifde_stats", "hifde_export_sets", "hifde_plan_replay", "hifde_profile",
+    "hifde_profile_read", "hifde_tree_free", "hifde_factor_free", "hifde_last_error",
 ]
+
+HIFDE_PROF_CELL_UP, HIFDE_PROF_CELL_DOWN, HIFDE_PROF_GROUP_UP, HIFDE_PROF_GROUP_DOWN = 0, 1, 2, 3
+HIFDE_PROF_TOP = 4
+HIFDE_PROF_CLASSES = 5
 
 
 class HifdeError(RuntimeError):
@@ -51,6 +55,15 @@ class Stats(C.Structure):
         ("skel_in", C.c_int64 * HIFDE_MAX_LEVELS),
         ("skel_out", C.c_int64 * HIFDE_MAX_LEVELS),
         ("max_front", C.c_int32 * HIFDE_MAX_LEVELS),
+    ]
+
+
+class Prof(C.Structure):
+    _fields_ = [
+        ("launches", C.c_int64),
+        ("ms", C.c_double),
+        ("bytes", C.c_double),
+        ("flops", C.c_double),
     ]
 
 
@@ -85,6 +98,8 @@ def lib():
     L.hifde_stats.argtypes = [vp, C.POINTER(Stats)]
     L.hifde_export_sets.argtypes = [vp, i32, C.POINTER(Sets)]
     L.hifde_plan_replay.argtypes = [vp, vp, C.POINTER(vp)]
+    L.hifde_profile.argtypes = [vp, C.c_uint32, i32]
+    L.hifde_profile_read.argtypes = [vp, i32, C.POINTER(Prof)]
     L.hifde_tree_free.argtypes = [vp]
     L.hifde_factor_free.argtypes = [vp]
     L.hifde_last_error.restype = C.c_char_p

@@ -116,6 +116,8 @@ struct CellStatic {
   int64_t elems = 0;
   int pmax = 0, smax = 0, ncell = 0;
   bool on_device = false;
+  // sweep work per color: apply-form elements p(p+1)/2 + (s-p)p, rows s, p
+  double fac[2] = {0, 0}, srows[2] = {0, 0}, prows[2] = {0, 0};
 };
 
 // Device description of the groups of one level (before the IDs).
@@ -160,6 +162,9 @@ struct GroupLevel {
   int nskel = 0, ngroup = 0, ncskel = 0;
   void* gscratch = nullptr;
   int64_t gstride = 0;
+  // sweep work of the skeletonized groups: apply-form elements
+  // r(r+1)/2 + kr, interpolation elements kr, rows |c| and r
+  double fac = 0, tel = 0, crows = 0, rrows = 0;
 };
 
 }  // namespace hifde
@@ -189,6 +194,23 @@ struct hifde_factor_s {
   DevMem X;
   DevMem pcg;
   int64_t pcg_rhs = 0;
+  // kernel timing (hifde_profile)
+  struct ProfEvent {
+    hipEvent_t a = nullptr, b = nullptr;
+    int cls = 0;
+    double bytes = 0, flops = 0;
+  };
+  uint32_t prof_mask = 0;
+  int prof_level = -1;
+  std::vector<ProfEvent> prof_ev;
+  size_t prof_used = 0;
+  hifde_prof_t prof_acc[HIFDE_PROF_CLASSES]{};
+  ~hifde_factor_s() {
+    for (ProfEvent& e : prof_ev) {
+      if (e.a) (void)hipEventDestroy(e.a);
+      if (e.b) (void)hipEventDestroy(e.b);
+    }
+  }
 };
 
 static thread_local std::string g_last_error;
@@ -278,6 +300,10 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
     cs->idx_h.insert(cs->idx_h.end(), c.p.begin(), c.p.end());
     cs->idx_h.insert(cs->idx_h.end(), c.q.begin(), c.q.end());
     f.color = c.color;
+    const int cc = c.color & 1;
+    cs->fac[cc] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
+    cs->srows[cc] += f.s;
+    cs->prows[cc] += f.p;
     off += int64_t(f.s) * f.s;
     cs->pmax = std::max(cs->pmax, f.p);
     cs->smax = std::max(cs->smax, f.s);
@@ -579,6 +605,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.idx_h.clear();
   G.ff.clear();
   G.ncskel = 0;
+  G.fac = G.tel = G.crows = G.rrows = 0;
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];
@@ -588,6 +615,13 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     d.skel = (k < d.nc) ? 1 : 0;
     if (!d.skel) continue;
     d.fg_off = fg_off;
+    {
+      const double r = d.nc - k;
+      G.fac += 0.5 * r * (r + 1) + double(k) * r;
+      G.tel += double(k) * r;
+      G.crows += d.nc;
+      G.rrows += r;
+    }
     FrontDev f{};
     f.off = fg_off;
     f.s = d.nc;
@@ -709,50 +743,138 @@ static void fill_stats(hifde_factor_s& F) {
 }
 
 // ---------------------------------------------------------------------------
+// Kernel timing: events around the launches of the profiled classes.
+// ---------------------------------------------------------------------------
+static void prof_collect(hifde_factor_s& F) {
+  for (size_t i = 0; i < F.prof_used; ++i) {
+    hifde_factor_s::ProfEvent& e = F.prof_ev[i];
+    HIP_CHECK(hipEventSynchronize(e.b));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e.a, e.b));
+    hifde_prof_t& acc = F.prof_acc[e.cls];
+    acc.launches += 1;
+    acc.ms += ms;
+    acc.bytes += e.bytes;
+    acc.flops += e.flops;
+  }
+  F.prof_used = 0;
+}
+
+template <class Launch>
+static void timed(hifde_factor_s& F, int cls, int level, double bytes, double flops,
+                  hipStream_t st, Launch&& launch) {
+  if (!((F.prof_mask >> cls) & 1u) || (F.prof_level >= 0 && F.prof_level != level)) {
+    launch();
+    return;
+  }
+  if (F.prof_used == 4096) prof_collect(F);
+  if (F.prof_used == F.prof_ev.size()) {
+    hifde_factor_s::ProfEvent e;
+    HIP_CHECK(hipEventCreate(&e.a));
+    HIP_CHECK(hipEventCreate(&e.b));
+    F.prof_ev.push_back(e);
+  }
+  hifde_factor_s::ProfEvent& e = F.prof_ev[F.prof_used++];
+  e.cls = cls;
+  e.bytes = bytes;
+  e.flops = flops;
+  HIP_CHECK(hipEventRecord(e.a, st));
+  launch();
+  HIP_CHECK(hipEventRecord(e.b, st));
+}
+
+// Algorithmic work of one cell sweep launch over the cells of `color` (-1:
+// all): the apply-form block is read once, the index list once, and the
+// vector rows as the step formulas touch them.
+struct Work {
+  double bytes, flops;
+};
+static Work cell_work(const CellStatic& S, int color, bool up, int nrhs, size_t esz, size_t xsz) {
+  double fac = 0, sr = 0, pr = 0;
+  for (int c = 0; c < 2; ++c)
+    if (color < 0 || color == c) {
+      fac += S.fac[c];
+      sr += S.srows[c];
+      pr += S.prows[c];
+    }
+  if (up) return {fac * esz + sr * 4 + 2 * sr * nrhs * xsz, 2.0 * nrhs * fac};
+  return {(fac - pr) * esz + sr * 4 + (sr + pr) * nrhs * xsz, 2.0 * nrhs * (fac - pr)};
+}
+static Work group_work(const GroupLevel& G, bool up, int nrhs, size_t esz, size_t xsz) {
+  const double fac = up ? G.fac : G.fac - G.rrows;
+  return {(fac + G.tel) * esz + G.crows * 4 + 2 * G.crows * nrhs * xsz,
+          2.0 * nrhs * (fac + G.tel)};
+}
+
+// ---------------------------------------------------------------------------
 // F^-1 application on unknown-major vectors X (type TX).
 // ---------------------------------------------------------------------------
 template <typename T, typename TX>
 static void apply_inverse(hifde_factor_s& F, TX* X, int nrhs, hipStream_t st) {
   const int L = F.g.L;
+  const size_t esz = sizeof(T), xsz = sizeof(TX);
   int cap;
   size_t smem;
   for (int l = 0; l < L; ++l) {
     CellLevel& C = F.cl[l];
     const CellStatic& S = *C.st;
     solve_lds<T>(S.smax + 4, nrhs, &cap, &smem);
-    for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL((k_cell_up<T, TX>), dim3(S.ncell), dim3(kThreads), smem, st, X, nrhs,
-                         static_cast<const T*>(C.pool), S.fronts, S.idx, color, cap,
-                         static_cast<T*>(C.gscratch), C.gstride);
+    for (int color = 0; color < 2; ++color) {
+      const Work w = F.prof_mask ? cell_work(S, color, true, nrhs, esz, xsz) : Work{0, 0};
+      timed(F, HIFDE_PROF_CELL_UP, l, w.bytes, w.flops, st, [&] {
+        hipLaunchKernelGGL((k_cell_up<T, TX>), dim3(S.ncell), dim3(kThreads), smem, st, X, nrhs,
+                           static_cast<const T*>(C.pool), S.fronts, S.idx, color, cap,
+                           static_cast<T*>(C.gscratch), C.gstride);
+      });
+    }
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
       solve_lds<T>(2 * G.ncskel + 4, nrhs, &cap, &smem);
-      hipLaunchKernelGGL((k_group_up<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
-                         static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool), G.groups,
-                         G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+      const Work w = F.prof_mask ? group_work(G, true, nrhs, esz, xsz) : Work{0, 0};
+      timed(F, HIFDE_PROF_GROUP_UP, l, w.bytes, w.flops, st, [&] {
+        hipLaunchKernelGGL((k_group_up<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
+                           static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool), G.groups,
+                           G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+      });
     }
   }
   CellLevel& top = F.cl[L];
   solve_lds<double>(top.st->smax + 4, nrhs, &cap, &smem);
-  hipLaunchKernelGGL((k_cell_up<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st, X,
-                     nrhs, static_cast<const double*>(top.pool), top.st->fronts, top.st->idx, -1,
-                     cap, static_cast<double*>(top.gscratch), top.gstride);
-  hipLaunchKernelGGL((k_cell_down<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st, X,
-                     nrhs, static_cast<const double*>(top.pool), top.st->fronts, top.st->idx, cap,
-                     static_cast<double*>(top.gscratch), top.gstride);
+  {
+    const Work w = F.prof_mask ? cell_work(*top.st, -1, true, nrhs, 8, xsz) : Work{0, 0};
+    timed(F, HIFDE_PROF_TOP, L, w.bytes, w.flops, st, [&] {
+      hipLaunchKernelGGL((k_cell_up<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st,
+                         X, nrhs, static_cast<const double*>(top.pool), top.st->fronts,
+                         top.st->idx, -1, cap, static_cast<double*>(top.gscratch), top.gstride);
+    });
+  }
+  {
+    const Work w = F.prof_mask ? cell_work(*top.st, -1, false, nrhs, 8, xsz) : Work{0, 0};
+    timed(F, HIFDE_PROF_TOP, L, w.bytes, w.flops, st, [&] {
+      hipLaunchKernelGGL((k_cell_down<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st,
+                         X, nrhs, static_cast<const double*>(top.pool), top.st->fronts,
+                         top.st->idx, cap, static_cast<double*>(top.gscratch), top.gstride);
+    });
+  }
   for (int l = L - 1; l >= 0; --l) {
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
       solve_lds<T>(2 * G.ncskel + 4, nrhs, &cap, &smem);
-      hipLaunchKernelGGL((k_group_down<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
-                         static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool), G.groups,
-                         G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+      const Work w = F.prof_mask ? group_work(G, false, nrhs, esz, xsz) : Work{0, 0};
+      timed(F, HIFDE_PROF_GROUP_DOWN, l, w.bytes, w.flops, st, [&] {
+        hipLaunchKernelGGL((k_group_down<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X,
+                           nrhs, static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool),
+                           G.groups, G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+      });
     }
     CellLevel& C = F.cl[l];
     solve_lds<T>(C.st->smax + 4, nrhs, &cap, &smem);
-    hipLaunchKernelGGL((k_cell_down<T, TX>), dim3(C.st->ncell), dim3(kThreads), smem, st, X, nrhs,
-                       static_cast<const T*>(C.pool), C.st->fronts, C.st->idx, cap,
-                       static_cast<T*>(C.gscratch), C.gstride);
+    const Work w = F.prof_mask ? cell_work(*C.st, -1, false, nrhs, esz, xsz) : Work{0, 0};
+    timed(F, HIFDE_PROF_CELL_DOWN, l, w.bytes, w.flops, st, [&] {
+      hipLaunchKernelGGL((k_cell_down<T, TX>), dim3(C.st->ncell), dim3(kThreads), smem, st, X,
+                         nrhs, static_cast<const T*>(C.pool), C.st->fronts, C.st->idx, cap,
+                         static_cast<T*>(C.gscratch), C.gstride);
+    });
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -887,6 +1009,25 @@ int hifde_stats(hifde_factor_t F, hifde_stats_t* out) {
   if (!F || !out) return fail(HIFDE_EINVAL, "NULL argument");
   *out = F->stats;
   return HIFDE_OK;
+}
+
+int hifde_profile(hifde_factor_t F, uint32_t class_mask, int level) {
+  if (!F) return fail(HIFDE_EINVAL, "NULL factor");
+  if (class_mask >> HIFDE_PROF_CLASSES) return fail(HIFDE_EINVAL, "unknown kernel class");
+  if (level < -1 || level > F->g.L) return fail(HIFDE_EINVAL, "level out of range");
+  F->prof_mask = class_mask;
+  F->prof_level = level;
+  return HIFDE_OK;
+}
+
+int hifde_profile_read(hifde_factor_t F, int cls, hifde_prof_t* out) {
+  if (!F || !out) return fail(HIFDE_EINVAL, "NULL argument");
+  if (cls < 0 || cls >= HIFDE_PROF_CLASSES) return fail(HIFDE_EINVAL, "unknown kernel class");
+  return guarded([&] {
+    prof_collect(*F);
+    *out = F->prof_acc[cls];
+    F->prof_acc[cls] = hifde_prof_t{};
+  });
 }
 
 int hifde_export_sets(hifde_factor_t F, int level2, hifde_sets_t* out) {
