@@ -106,19 +106,20 @@ def pmc_summary(fetch_dir, write_dir, workload):
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _pmc_rows(d, counter)
         # per dispatch: the counter is reported per dispatch (summed over instances)
-        copy = [v for n, g, v in rows if "copy" in n.lower()]
+        wide = [v for n, g, v in rows if "copybuffer" in n.lower()]
+        narrow = [v for n, g, v in rows if "MulFunctor" in n]
         dom = [v for n, g, v in rows if DOMINANT_KERNEL.replace(" ", "") in n.replace(" ", "")]
-        if not copy or not dom:
-            raise SystemExit(f"{counter}: calibration copy or {DOMINANT_KERNEL} not found in {d}")
-        copy_kib = max(copy)
-        scale = (CALIB_COPY_BYTES / 1024.0) / copy_kib
-        out[key] = (len(dom), float(np.mean(dom)), scale)
-    nd, fkib, fs = out["fetch"]
-    _, wkib, ws = out["write"]
+        if not wide or not narrow or not dom:
+            raise SystemExit(f"{counter}: calibration copies or {DOMINANT_KERNEL} not found in {d}")
+        kib = CALIB_COPY_BYTES / 1024.0
+        out[key] = (len(dom), float(np.mean(dom)), kib / max(narrow), kib / max(wide))
+    nd, fkib, fs, fs_w = out["fetch"]
+    _, wkib, ws, ws_w = out["write"]
     traffic = (fkib * fs + wkib * ws) * 1024.0
     lines = [
         f"# HBM traffic of {DOMINANT_KERNEL} on {workload} from rocprofv3 counters",
-        "# commands (from the repository root, TMPDIR=/tmp):",
+        "# commands (from the repository root, TMPDIR=/tmp); the scales divide the known",
+        "# size of a 4-byte-per-lane elementwise copy by what the counter reads for it",
         f"#   rocprofv3 --pmc FETCH_SIZE -f csv -d <FETCH_DIR> -- python bench.py --steps 1 "
         f"--warmup 0 --no-cpu --no-fp64 --calib-copy",
         f"#   rocprofv3 --pmc WRITE_SIZE -f csv -d <WRITE_DIR> -- python bench.py --steps 1 "
@@ -131,6 +132,9 @@ def pmc_summary(fetch_dir, write_dir, workload):
         f"write_kib_per_dispatch: {wkib:.1f}",
         f"copy_fetch_scale: {fs:.4f}",
         f"copy_write_scale: {ws:.4f}",
+        f"# the same counters on the runtime's block copy (wide loads) give scales "
+        f"{fs_w:.4f} (fetch) and {ws_w:.4f} (write)",
+        f"traffic_bytes_per_launch_wide_scale: {(fkib * fs_w + wkib * ws_w) * 1024.0:.0f}",
         f"traffic_bytes_per_launch: {traffic:.0f}",
     ]
     return "\n".join(lines)
@@ -190,9 +194,13 @@ def main():
     prec = H.HIFDE_MIXED if w.precision == "mixed" else H.HIFDE_FP64
 
     if args.calib_copy:
-        src = torch.ones(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        # two plain copies of known size: a runtime block copy (wide loads)
+        # and an elementwise scale by 1 on 4-byte-misaligned views, which
+        # runs with one 4-byte load and store per lane like the sweep kernels
+        src = torch.ones(CALIB_COPY_BYTES // 4 + 1, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        dst[:-1].copy_(src[:-1])
+        torch.mul(src[1:], 1.0, out=dst[1:])
         torch.cuda.synchronize()
         del src, dst
 

@@ -2,9 +2,45 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 
 namespace hifde {
+
+// Runs f(i, worker) for i in [0, n) on up to `workers` threads, `grain`
+// consecutive items at a time; the first exception is rethrown here.
+template <class F>
+static void parallel_for(size_t n, size_t grain, int workers, F&& f) {
+  size_t chunks = (n + grain - 1) / grain;
+  int nt = int(std::min<size_t>(size_t(workers), chunks));
+  if (nt <= 1) {
+    for (size_t i = 0; i < n; ++i) f(i, 0);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::exception_ptr err;
+  std::atomic<bool> failed{false};
+  auto body = [&](int w) {
+    try {
+      for (;;) {
+        const size_t b = next.fetch_add(grain);
+        if (b >= n || failed.load()) break;
+        const size_t e = std::min(n, b + grain);
+        for (size_t i = b; i < e; ++i) f(i, w);
+      }
+    } catch (...) {
+      if (!failed.exchange(true)) err = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nt; ++w) th.emplace_back(body, w);
+  body(0);
+  for (auto& t : th) t.join();
+  if (err) std::rethrow_exception(err);
+}
 
 std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
   if (dim != 2 && dim != 3) return "dim must be 2 or 3";
@@ -35,7 +71,9 @@ std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
 Planner::Planner(const Geom& g) : g_(g) {
   active_.assign(g_.N, 1);
   grouped_.assign(g_.N, 0);
-  loc_.assign(g_.N, -1);
+  workers_ = int(std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())));
+  if (const char* e = std::getenv("HIFDE_PLAN_THREADS")) workers_ = std::max(1, std::atoi(e));
+  loc_.resize(workers_);
   own0_.assign(g_.N, -1);
   own1_.assign(g_.N, -1);
   act_.resize(g_.N);
@@ -105,6 +143,24 @@ void Planner::for_neighbors(int64_t d, F&& f) const {
 
 static inline int64_t link_ref(int64_t N, int64_t lo, int k) { return N * (1 + k) + lo; }
 
+// Start of every per-item map list in the concatenation of `parts`
+// (reported through shift(i, start)); returns the total length.
+template <class Shift>
+static int64_t concat_offsets(const std::vector<std::vector<int32_t>>& parts, Shift&& shift) {
+  int64_t base = 0;
+  for (size_t i = 0; i < parts.size(); ++i) {
+    shift(i, base);
+    base += int64_t(parts[i].size());
+  }
+  return base;
+}
+
+int32_t* Planner::loc(int w) {
+  std::vector<int32_t>& v = loc_[w];
+  if (v.empty()) v.assign(g_.N, -1);
+  return v.data();
+}
+
 void Planner::drop_inactive() {
   size_t w = 0;
   for (size_t i = 0; i < act_.size(); ++i)
@@ -145,12 +201,16 @@ void Planner::build_cells(int l, LevelPlan& lp) {
   std::vector<int32_t> count(nbox + 1, 0);
   std::vector<int32_t> dofs;
   std::vector<int32_t> boxes;
-  for (int32_t d : act_)
-    if (interior(d)) {
-      int64_t b = box_of(d, l);
-      dofs.push_back(d);
-      boxes.push_back(int32_t(b));
-      ++count[b + 1];
+  std::vector<int32_t> keyv(act_.size());
+  parallel_for(act_.size(), 8192, workers_, [&](size_t i, int) {
+    const int32_t d = act_[i];
+    keyv[i] = interior(d) ? int32_t(box_of(d, l)) : -1;
+  });
+  for (size_t i = 0; i < act_.size(); ++i)
+    if (keyv[i] >= 0) {
+      dofs.push_back(act_[i]);
+      boxes.push_back(keyv[i]);
+      ++count[keyv[i] + 1];
     }
   for (int64_t b = 0; b < nbox; ++b) count[b + 1] += count[b];
   std::vector<int32_t> cell_of_box(nbox, -1);
@@ -196,8 +256,12 @@ void Planner::build_cells(int l, LevelPlan& lp) {
     }
   }
 
-  for (size_t ci = 0; ci < lp.cells.size(); ++ci) {
+  // Per cell (independent; maps are collected per cell and concatenated).
+  std::vector<std::vector<int32_t>> cmaps(lp.cells.size());
+  parallel_for(lp.cells.size(), 8, workers_, [&](size_t ci, int w) {
+    int32_t* loc_ = loc(w);
     Cell& C = lp.cells[ci];
+    std::vector<int32_t>& maps = cmaps[ci];
     // Front q^+: surviving fronts of the children that are not interior
     // here, plus active stencil neighbours of the interior.
     std::vector<int32_t> q;
@@ -221,22 +285,22 @@ void Planner::build_cells(int l, LevelPlan& lp) {
       const Level& prev = lv_[l - 1];
       for (int32_t k : kids[ci]) {
         const Cell& K = prev.cells()[k];
-        Source s{SRC_CELL_U, l - 1, k, int32_t(K.q.size()), int64_t(lp.maps.size()), 0};
+        Source s{SRC_CELL_U, l - 1, k, int32_t(K.q.size()), int64_t(maps.size()), 0};
         s.colmap = s.rowmap;
         for (int32_t z : K.q) {
           if (active_[z] && loc_[z] < 0)
             throw std::runtime_error("planner: child front unknown lost by its parent");
-          lp.maps.push_back(active_[z] ? loc_[z] : -1);
+          maps.push_back(active_[z] ? loc_[z] : -1);
         }
         C.src.push_back(s);
       }
       for (int32_t gi : gkids[ci]) {
         const auto& surv = prev.survivors(gi);
-        Source s{SRC_GROUP_BASE, l - 1, gi, int32_t(surv.size()), int64_t(lp.maps.size()), 0};
+        Source s{SRC_GROUP_BASE, l - 1, gi, int32_t(surv.size()), int64_t(maps.size()), 0};
         s.colmap = s.rowmap;
         for (int32_t z : surv) {
           if (loc_[z] < 0) throw std::runtime_error("planner: base unknown outside its cell");
-          lp.maps.push_back(loc_[z]);
+          maps.push_back(loc_[z]);
         }
         C.src.push_back(s);
       }
@@ -254,7 +318,17 @@ void Planner::build_cells(int l, LevelPlan& lp) {
     }
     for (int32_t d : C.p) loc_[d] = -1;
     for (int32_t d : C.q) loc_[d] = -1;
-  }
+  });
+  lp.maps.resize(concat_offsets(cmaps, [&](size_t i, int64_t base) {
+    for (Source& s : lp.cells[i].src) {
+      s.rowmap += base;
+      s.colmap += base;
+    }
+  }));
+  parallel_for(cmaps.size(), 64, workers_, [&](size_t i, int) {
+    if (!lp.cells[i].src.empty())
+      std::copy(cmaps[i].begin(), cmaps[i].end(), lp.maps.begin() + lp.cells[i].src[0].rowmap);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -282,12 +356,16 @@ void Planner::build_groups(int l, LevelPlan& lp) {
   for (int k = 0; k < g_.dim; ++k) nkey *= B;
   std::vector<int32_t> count(nkey + 1, 0), keys;
   std::vector<int32_t> dofs;
-  for (int32_t d : act_)
-    if (sigma(d, l) == 1) {
-      int64_t key = group_key(d, l);
-      dofs.push_back(d);
-      keys.push_back(int32_t(key));
-      ++count[key + 1];
+  std::vector<int32_t> keyv(act_.size());
+  parallel_for(act_.size(), 8192, workers_, [&](size_t i, int) {
+    const int32_t d = act_[i];
+    keyv[i] = sigma(d, l) == 1 ? int32_t(group_key(d, l)) : -1;
+  });
+  for (size_t i = 0; i < act_.size(); ++i)
+    if (keyv[i] >= 0) {
+      dofs.push_back(act_[i]);
+      keys.push_back(keyv[i]);
+      ++count[keyv[i] + 1];
     }
   for (int64_t b = 0; b < nkey; ++b) count[b + 1] += count[b];
   std::vector<int32_t> group_of_key(nkey, -1);
@@ -323,7 +401,10 @@ void Planner::build_groups(int l, LevelPlan& lp) {
       gkids[g].push_back(int32_t(gi));
     }
   }
-  for (size_t gi = 0; gi < lp.groups.size(); ++gi) {
+  std::vector<std::vector<int32_t>> gm(lp.groups.size());
+  parallel_for(lp.groups.size(), 16, workers_, [&](size_t gi, int w) {
+    int32_t* loc_ = loc(w);
+    std::vector<int32_t>& gmaps = gm[gi];
     Group& G = lp.groups[gi];
     const int32_t nc = int32_t(G.c.size());
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = i;
@@ -351,11 +432,11 @@ void Planner::build_groups(int l, LevelPlan& lp) {
       const Level& prev = lv_[l - 1];
       for (int32_t pg : gkids[gi]) {
         const auto& surv = prev.survivors(pg);
-        Source s{SRC_GROUP_BASE, l - 1, pg, int32_t(surv.size()), int64_t(lp.gmaps.size()), 0};
+        Source s{SRC_GROUP_BASE, l - 1, pg, int32_t(surv.size()), int64_t(gmaps.size()), 0};
         s.colmap = s.rowmap;
         for (int32_t z : surv) {
           if (loc_[z] < 0) throw std::runtime_error("planner: base unknown outside its group");
-          lp.gmaps.push_back(loc_[z]);
+          gmaps.push_back(loc_[z]);
         }
         G.bsrc.push_back(s);
       }
@@ -385,15 +466,31 @@ void Planner::build_groups(int l, LevelPlan& lp) {
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = nn + i;
     for (int32_t ci : adj) {
       const Cell& C = cells[ci];
-      Source s{SRC_CELL_U, l, ci, int32_t(C.q.size()), int64_t(lp.gmaps.size()), 0};
-      for (int32_t z : C.q) lp.gmaps.push_back(loc_[z]);
-      s.colmap = int64_t(lp.gmaps.size());
-      for (int32_t z : C.q) lp.gmaps.push_back(loc_[z] >= nn ? loc_[z] - nn : -1);
+      Source s{SRC_CELL_U, l, ci, int32_t(C.q.size()), int64_t(gmaps.size()), 0};
+      for (int32_t z : C.q) gmaps.push_back(loc_[z]);
+      s.colmap = int64_t(gmaps.size());
+      for (int32_t z : C.q) gmaps.push_back(loc_[z] >= nn ? loc_[z] - nn : -1);
       G.gsrc.push_back(s);
     }
     for (int32_t i = 0; i < nn; ++i) loc_[G.cN[i]] = -1;
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = -1;
-  }
+  });
+  std::vector<int64_t> gbase(lp.groups.size());
+  lp.gmaps.resize(concat_offsets(gm, [&](size_t i, int64_t base) {
+    gbase[i] = base;
+    Group& G = lp.groups[i];
+    for (Source& s : G.bsrc) {
+      s.rowmap += base;
+      s.colmap += base;
+    }
+    for (Source& s : G.gsrc) {
+      s.rowmap += base;
+      s.colmap += base;
+    }
+  }));
+  parallel_for(gm.size(), 64, workers_, [&](size_t i, int) {
+    std::copy(gm[i].begin(), gm[i].end(), lp.gmaps.begin() + gbase[i]);
+  });
   for (const Cell& C : cells)
     for (int32_t z : C.q) own0_[z] = own1_[z] = -1;
 }

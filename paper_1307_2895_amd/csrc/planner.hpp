@@ -139,7 +139,9 @@ class Planner {
   std::vector<int8_t> seplev_;       // highest level at which x is a separator
   std::vector<uint8_t> active_, grouped_;
   std::vector<int32_t> act_;         // sorted active unknowns
-  std::vector<int32_t> loc_;         // scratch: global -> local (-1)
+  int32_t* loc(int worker);           // worker's global -> local map (all -1)
+  int workers_ = 1;                  // planning threads
+  std::vector<std::vector<int32_t>> loc_;
   std::vector<int32_t> own0_, own1_; // scratch: fronts holding an unknown
   std::vector<Level> lv_;
   std::shared_ptr<LevelPlan> building0_;
