@@ -29,9 +29,10 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
-# The kernel the roofline object describes: the upward cell sweep of F^-1
-# (every launch of k_cell_up<float, float>, all levels and both colors).
-DOMINANT_KERNEL = "k_cell_up<float, float>"
+# The kernel the roofline object describes: the upward sweep of F^-1 over
+# cells and skeleton fronts (every launch of k_sweep_up<float, float, 1>:
+# all levels, both cell colors and the groups).
+DOMINANT_KERNEL = "k_sweep_up<float, float, 1>"
 DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
 CALIB_COPY_BYTES = 512 << 20
 
@@ -213,12 +214,12 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if profile:
-            H.hifde_profile(F, 1 << H.HIFDE_PROF_CELL_UP, -1)
+            H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP, -1)
         u, its, rel = H.hifde_pcg(F, f_d, tol=1e-12, maxit=200)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if profile:
-            r = H.hifde_profile_read(F, H.HIFDE_PROF_CELL_UP)
+            r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP)
             for k in prof:
                 prof[k] += r[k]
         st = H.hifde_stats(F)

@@ -148,13 +148,14 @@ int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
  * formulas of Section 4.1 need), so that achieved bandwidth can be compared
  * with the device's.  Profiling adds two event records per timed launch. */
 enum {
-  HIFDE_PROF_CELL_UP = 0,     /* upward cell step: x_p <- D^-1 L^-1 x_p,
-                                 x_q -= W^T L^-1 x_p (Lemma 2.1)            */
-  HIFDE_PROF_CELL_DOWN = 1,   /* downward cell step: x_p <- L^-T (x_p - W x_q) */
-  HIFDE_PROF_GROUP_UP = 2,    /* upward group step (Lemma 2.4)              */
-  HIFDE_PROF_GROUP_DOWN = 3,  /* downward group step                        */
-  HIFDE_PROF_TOP = 4,         /* both steps of the top block (double)       */
-  HIFDE_PROF_CLASSES = 5
+  HIFDE_PROF_SWEEP_UP = 0,    /* upward steps of cells and skeleton fronts:
+                                 z_p = D^-1 L^-1 x_p, x_q -= W^T L^-1 x_p
+                                 (Lemma 2.1; Lemma 2.4 after the interpolation) */
+  HIFDE_PROF_SWEEP_DOWN = 1,  /* downward steps: x_p = L^-T (z_p - W x_q)    */
+  HIFDE_PROF_INTERP = 2,      /* interpolation steps of skeletonized groups:
+                                 x_r -= T^T x_s (up), x_s -= T x_r (down)    */
+  HIFDE_PROF_TOP = 3,         /* both steps of the top block (double)       */
+  HIFDE_PROF_CLASSES = 4
 };
 
 typedef struct {

@@ -14,8 +14,8 @@ import numpy as np
 from ._lib import (  # noqa: F401
     HIFDE_FP64, HIFDE_MIXED, HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
-    HIFDE_PROF_CELL_UP, HIFDE_PROF_CELL_DOWN, HIFDE_PROF_GROUP_UP, HIFDE_PROF_GROUP_DOWN,
-    HIFDE_PROF_TOP, HIFDE_PROF_CLASSES,
+    HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
+    HIFDE_PROF_CLASSES,
 )
 
 

@@ -29,9 +29,8 @@ EXPORTED = [
     "hifde_profile_read", "hifde_tree_free", "hifde_factor_free", "hifde_last_error",
 ]
 
-HIFDE_PROF_CELL_UP, HIFDE_PROF_CELL_DOWN, HIFDE_PROF_GROUP_UP, HIFDE_PROF_GROUP_DOWN = 0, 1, 2, 3
-HIFDE_PROF_TOP = 4
-HIFDE_PROF_CLASSES = 5
+HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP = 0, 1, 2, 3
+HIFDE_PROF_CLASSES = 4
 
 
 class HifdeError(RuntimeError):

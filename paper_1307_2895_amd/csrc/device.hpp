@@ -45,6 +45,15 @@ struct FrontDev {
   int32_t pad;
 };
 
+// A front as the F^-1 sweeps see it: packed apply-form tiles at element
+// `off` of the packed pool, D^-1 at `dv`, unknown list at `idx`.
+struct PackDev {
+  int64_t off;
+  int64_t dv;
+  int64_t idx;
+  int32_t s, p;
+};
+
 // A skeletonization group.
 struct GroupDev {
   int64_t gw_off;    // [c^N; c] x c workspace (ld = nn + nc)

@@ -99,6 +99,54 @@ struct Arena {
   }
 };
 
+// Packed fronts and work lists of the F^-1 sweeps over one set of fronts:
+// the cells of a level (two colors), the skeletonized groups of a level, or
+// the top block.  Also the algorithmic work of each launch (for profiling).
+struct SweepSet {
+  std::vector<PackDev> ph;
+  std::vector<int2> up_h[2], down_h;
+  int64_t pk_elems = 0, dv_elems = 0;
+  int kup = 0, kdown = 0;            // rows of x one work-group stages at most
+  double fac[2] = {0, 0}, srows[2] = {0, 0}, prows[2] = {0, 0};
+  PackDev* packs = nullptr;
+  int2* up[2] = {nullptr, nullptr};
+  int2* down = nullptr;
+};
+
+static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool colored) {
+  S = SweepSet{};
+  for (const FrontDev& f : fh) {
+    PackDev q{};
+    q.off = S.pk_elems;
+    q.dv = S.dv_elems;
+    q.idx = f.idx;
+    q.s = f.s;
+    q.p = f.p;
+    S.pk_elems += packed_tiles(f.s, f.p) * 256;
+    S.dv_elems += f.p;
+    const int fi = int(S.ph.size());
+    S.ph.push_back(q);
+    const int c = colored ? (f.color & 1) : 0;
+    const int rt = (f.s + 15) >> 4, P16 = (f.p + 15) >> 4;
+    for (int t = 0; t < rt; t += kSwWaves) {
+      S.up_h[c].push_back(make_int2(fi, t));
+      S.kup = std::max(S.kup, std::min(f.p, 16 * std::min(P16, std::min(rt, t + kSwWaves))));
+    }
+    for (int t = 0; t < P16; t += kSwWaves) S.down_h.push_back(make_int2(fi, t));
+    S.kdown = std::max(S.kdown, 16 * rt);
+    S.fac[c] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
+    S.srows[c] += f.s;
+    S.prows[c] += f.p;
+  }
+}
+
+static void upload_sweep(SweepSet& S, Arena& mem, hipStream_t st) {
+  S.packs = mem.upload(S.ph, st);
+  S.up[0] = mem.upload(S.up_h[0], st);
+  S.up[1] = mem.upload(S.up_h[1], st);
+  S.down = mem.upload(S.down_h, st);
+}
+
 // Device description of the cells of one level; depends on the plan only, so
 // the level-0 one is shared by every factorization of a tree.
 struct CellStatic {
@@ -116,8 +164,7 @@ struct CellStatic {
   int64_t elems = 0;
   int pmax = 0, smax = 0, ncell = 0;
   bool on_device = false;
-  // sweep work per color: apply-form elements p(p+1)/2 + (s-p)p, rows s, p
-  double fac[2] = {0, 0}, srows[2] = {0, 0}, prows[2] = {0, 0};
+  SweepSet sw;                       // F^-1 sweeps (two colors)
 };
 
 // Device description of the groups of one level (before the IDs).
@@ -144,8 +191,7 @@ struct CellLevel {
   std::shared_ptr<CellStatic> st;
   void* pool = nullptr;              // frontal matrices
   int* info = nullptr;
-  void* gscratch = nullptr;          // x staging for fronts too tall for LDS
-  int64_t gstride = 0;
+  void *pk = nullptr, *dinv = nullptr;  // packed apply form, D^-1
 };
 
 struct GroupLevel {
@@ -160,11 +206,10 @@ struct GroupLevel {
   std::vector<int32_t> gsel_h, idx_h;
   int64_t perm_stride = 0;
   int nskel = 0, ngroup = 0, ncskel = 0;
-  void* gscratch = nullptr;
-  int64_t gstride = 0;
-  // sweep work of the skeletonized groups: apply-form elements
-  // r(r+1)/2 + kr, interpolation elements kr, rows |c| and r
-  double fac = 0, tel = 0, crows = 0, rrows = 0;
+  SweepSet sw;                       // F^-1 sweeps over the skeleton fronts
+  void *pk = nullptr, *dinv = nullptr;
+  // interpolation work: elements kr, rows r and k
+  double tel = 0, rrows = 0, krows = 0;
 };
 
 }  // namespace hifde
@@ -191,7 +236,7 @@ struct hifde_factor_s {
   DevMem diag, offd;
   hifde_stats_t stats{};
   // solver scratch
-  DevMem X;
+  DevMem X, Z;
   DevMem pcg;
   int64_t pcg_rhs = 0;
   // kernel timing (hifde_profile)
@@ -300,10 +345,6 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
     cs->idx_h.insert(cs->idx_h.end(), c.p.begin(), c.p.end());
     cs->idx_h.insert(cs->idx_h.end(), c.q.begin(), c.q.end());
     f.color = c.color;
-    const int cc = c.color & 1;
-    cs->fac[cc] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
-    cs->srows[cc] += f.s;
-    cs->prows[cc] += f.p;
     off += int64_t(f.s) * f.s;
     cs->pmax = std::max(cs->pmax, f.p);
     cs->smax = std::max(cs->smax, f.s);
@@ -312,6 +353,7 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
   cs->elems = off;
   cs->ncell = int(cs->fh.size());
   cs->maps_h = &lp.maps;
+  build_sweep(cs->sw, cs->fh, true);
   return cs;
 }
 
@@ -322,6 +364,7 @@ static void upload_cell_static(CellStatic& cs, hipStream_t st) {
   cs.maps = cs.mem.upload(*cs.maps_h, st);
   cs.trips = cs.mem.upload(cs.trips_h, st);
   cs.idx = cs.mem.upload(cs.idx_h, st);
+  upload_sweep(cs.sw, cs.mem, st);
   cs.on_device = true;
 }
 
@@ -439,7 +482,19 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
     hipLaunchKernelGGL(k_inv_commit<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
                        toff_d);
   }
-  hipLaunchKernelGGL(k_inv_finish<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d);
+  HIP_CHECK(hipGetLastError());
+}
+
+// Packed apply form and D^-1 of every front (the sweeps' copy).
+template <typename T>
+static void pack_fronts(Arena& mem, const T* pool, const std::vector<FrontDev>& fh,
+                        const FrontDev* fronts_d, const SweepSet& S, void** pk, void** dinv,
+                        hipStream_t st) {
+  *pk = mem.get<T>(size_t(std::max<int64_t>(S.pk_elems, 1)));
+  *dinv = mem.get<T>(size_t(std::max<int64_t>(S.dv_elems, 1)));
+  if (fh.empty()) return;
+  hipLaunchKernelGGL(k_pack<T>, dim3(unsigned(fh.size())), dim3(kThreads), 0, st, pool, fronts_d,
+                     S.packs, static_cast<T*>(*pk), static_cast<T*>(*dinv));
   HIP_CHECK(hipGetLastError());
 }
 
@@ -455,30 +510,10 @@ static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
 }
 
 // Elements of x a solve work-group can stage in LDS.
-template <typename T>
-static int lds_x_capacity() {
-  return kSolveLdsBytes / int(sizeof(T));
-}
 
 // Scratch for solve kernels whose x does not fit in LDS.
-template <typename T>
-static void solve_scratch(Arena& mem, int nblocks, int smax, void** ptr, int64_t* stride) {
-  if (smax <= lds_x_capacity<T>()) return;
-  *stride = int64_t(smax) * kMaxRhsChunk;
-  *ptr = mem.get<T>(size_t(*stride) * std::max(1, nblocks));
-}
 
 // LDS sizing of one solve launch: x capacity (elements) and bytes.
-template <typename T>
-static void solve_lds(int smax, int nrhs, int* cap, size_t* bytes) {
-  const int cmax = lds_x_capacity<T>();
-  if (smax > cmax) {
-    *cap = cmax;
-  } else {
-    *cap = smax * rhs_chunk(smax, nrhs, cmax);
-  }
-  *bytes = size_t(*cap) * sizeof(T);
-}
 
 // ---------------------------------------------------------------------------
 // Cells of level l: plan, assemble, factor.
@@ -507,7 +542,6 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   HIP_CHECK(hipMemsetAsync(D.pool, 0, size_t(S.elems) * sizeof(T), st));
   D.info = F.mem.get<int>(std::max(1, S.ncell));
   HIP_CHECK(hipMemsetAsync(D.info, 0, sizeof(int) * std::max(1, S.ncell), st));
-  solve_scratch<T>(F.mem, S.ncell, S.smax + 4, &D.gscratch, &D.gstride);
   PoolTable pt = pools_for_level(F, l - 1);
   if (S.ncell > 0)
     hipLaunchKernelGGL((k_assemble<T, TS>), dim3(S.ncell), dim3(kThreads), 0, st,
@@ -516,6 +550,7 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   HIP_CHECK(hipGetLastError());
   batched_ldl<T>(static_cast<T*>(D.pool), S.fh, S.fronts, D.info, st);
   apply_form<T>(F.mem, static_cast<T*>(D.pool), S.fh, S.fronts, st);
+  pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.dinv, st);
 }
 
 static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
@@ -605,7 +640,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.idx_h.clear();
   G.ff.clear();
   G.ncskel = 0;
-  G.fac = G.tel = G.crows = G.rrows = 0;
+  G.tel = G.rrows = G.krows = 0;
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];
@@ -615,17 +650,14 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     d.skel = (k < d.nc) ? 1 : 0;
     if (!d.skel) continue;
     d.fg_off = fg_off;
-    {
-      const double r = d.nc - k;
-      G.fac += 0.5 * r * (r + 1) + double(k) * r;
-      G.tel += double(k) * r;
-      G.crows += d.nc;
-      G.rrows += r;
-    }
+    G.tel += double(k) * (d.nc - k);
+    G.rrows += d.nc - k;
+    G.krows += k;
     FrontDev f{};
     f.off = fg_off;
     f.s = d.nc;
     f.p = d.nc - k;
+    f.idx = int64_t(G.idx_h.size());
     G.ff.push_back(f);
     fg_off += int64_t(d.nc) * d.nc;
     d.idx = int64_t(G.idx_h.size());
@@ -647,7 +679,6 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.fgfronts = F.mem.upload(G.ff, st);
   G.info = F.mem.get<int>(G.ff.size());
   HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ff.size(), st));
-  solve_scratch<T>(F.mem, G.nskel, 2 * G.ncskel + 4, &G.gscratch, &G.gstride);
   hipLaunchKernelGGL(k_group_front<T>, dim3(G.nskel), dim3(kThreads), 0, st,
                      static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
                      static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
@@ -655,6 +686,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   HIP_CHECK(hipGetLastError());
   batched_ldl<T>(static_cast<T*>(G.fg), G.ff, G.fgfronts, G.info, st);
   apply_form<T>(F.mem, static_cast<T*>(G.fg), G.ff, G.fgfronts, st);
+  build_sweep(G.sw, G.ff, false);
+  upload_sweep(G.sw, F.mem, st);
+  pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.dinv, st);
 }
 
 template <typename T>
@@ -783,13 +817,15 @@ static void timed(hifde_factor_s& F, int cls, int level, double bytes, double fl
   HIP_CHECK(hipEventRecord(e.b, st));
 }
 
-// Algorithmic work of one cell sweep launch over the cells of `color` (-1:
-// all): the apply-form block is read once, the index list once, and the
-// vector rows as the step formulas touch them.
+// Algorithmic work of one sweep launch over the fronts of color c (-1: all)
+// of a set: the apply-form elements p(p+1)/2 + (s-p)p (D^-1 included) are
+// read once, the unknown lists once, and the vector rows as the step
+// formulas touch them (up: read s rows, write s rows; down: read s rows,
+// write p rows).
 struct Work {
   double bytes, flops;
 };
-static Work cell_work(const CellStatic& S, int color, bool up, int nrhs, size_t esz, size_t xsz) {
+static Work sweep_work(const SweepSet& S, int color, bool up, int nrhs, size_t esz, size_t xsz) {
   double fac = 0, sr = 0, pr = 0;
   for (int c = 0; c < 2; ++c)
     if (color < 0 || color == c) {
@@ -800,81 +836,128 @@ static Work cell_work(const CellStatic& S, int color, bool up, int nrhs, size_t 
   if (up) return {fac * esz + sr * 4 + 2 * sr * nrhs * xsz, 2.0 * nrhs * fac};
   return {(fac - pr) * esz + sr * 4 + (sr + pr) * nrhs * xsz, 2.0 * nrhs * (fac - pr)};
 }
-static Work group_work(const GroupLevel& G, bool up, int nrhs, size_t esz, size_t xsz) {
-  const double fac = up ? G.fac : G.fac - G.rrows;
-  return {(fac + G.tel) * esz + G.crows * 4 + 2 * G.crows * nrhs * xsz,
-          2.0 * nrhs * (fac + G.tel)};
+// Interpolation step of a level's groups: T (kr elements) once, the
+// skeleton (up) or redundant (down) rows read, the other rows updated.
+static Work interp_work(const GroupLevel& G, bool up, int nrhs, size_t esz, size_t xsz) {
+  const double rd = up ? G.krows : G.rrows, rw = up ? G.rrows : G.krows;
+  return {G.tel * esz + (G.rrows + G.krows) * 4 + (rd + 2 * rw) * nrhs * xsz,
+          2.0 * nrhs * G.tel};
+}
+
+// Launch shape of a sweep: NT = 16-column tiles of right-hand sides per
+// work-group, the LDS rows of one staging chunk (at most 32 KiB), the grid.
+constexpr int kSwLdsCap = 32 * 1024;
+struct SweepShape {
+  int NT, nch, kch;
+  size_t lds;
+  unsigned grid;
+};
+template <typename T>
+static SweepShape sweep_shape(int nitems, int nrhs, int krows) {
+  SweepShape g{};
+  g.NT = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4;
+  g.nch = (nrhs + 16 * g.NT - 1) / (16 * g.NT);
+  const int stride = sweep_stride(g.NT);
+  const int cap = (kSwLdsCap / (stride * int(sizeof(T)))) & ~15;
+  g.kch = std::min(cap, std::max(16, (krows + 15) & ~15));
+  g.lds = size_t(g.kch) * stride * sizeof(T);
+  const int64_t grid = int64_t(8) * ((nitems + 7) / 8) * g.nch;
+  if (grid > INT32_MAX) throw Error(HIFDE_EINVAL, "sweep grid too large");
+  g.grid = unsigned(grid);
+  return g;
+}
+
+template <typename T, typename TX>
+static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, int c,
+                     const void* pk, const void* dinv, const int32_t* idx, TX* X, TX* Z, int nrhs,
+                     hipStream_t st) {
+  const int n = int(S.up_h[c].size());
+  if (n == 0) return;
+  const SweepShape g = sweep_shape<T>(n, nrhs, S.kup);
+  const Work w = F.prof_mask ? sweep_work(S, c, true, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
+  const T* P = static_cast<const T*>(pk);
+  const T* Dv = static_cast<const T*>(dinv);
+  timed(F, cls, level, w.bytes, w.flops, st, [&] {
+    switch (g.NT) {
+      case 1:
+        hipLaunchKernelGGL((k_sweep_up<T, TX, 1>), dim3(g.grid), dim3(kThreads), g.lds, st,
+                           S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_sweep_up<T, TX, 2>), dim3(g.grid), dim3(kThreads), g.lds, st,
+                           S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch);
+        break;
+      default:
+        hipLaunchKernelGGL((k_sweep_up<T, TX, 4>), dim3(g.grid), dim3(kThreads), g.lds, st,
+                           S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch);
+    }
+  });
+}
+
+template <typename T, typename TX>
+static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S, const void* pk,
+                       const int32_t* idx, TX* X, const TX* Z, int nrhs, hipStream_t st) {
+  const int n = int(S.down_h.size());
+  if (n == 0) return;
+  const SweepShape g = sweep_shape<T>(n, nrhs, S.kdown);
+  const Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
+  const T* P = static_cast<const T*>(pk);
+  timed(F, cls, level, w.bytes, w.flops, st, [&] {
+    switch (g.NT) {
+      case 1:
+        hipLaunchKernelGGL((k_sweep_down<T, TX, 1>), dim3(g.grid), dim3(kThreads), g.lds, st,
+                           S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_sweep_down<T, TX, 2>), dim3(g.grid), dim3(kThreads), g.lds, st,
+                           S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch);
+        break;
+      default:
+        hipLaunchKernelGGL((k_sweep_down<T, TX, 4>), dim3(g.grid), dim3(kThreads), g.lds, st,
+                           S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
-// F^-1 application on unknown-major vectors X (type TX).
+// F^-1 application on unknown-major vectors X (type TX); Z (same size) holds
+// the values z_p of the eliminated unknowns between the two sweeps.
 // ---------------------------------------------------------------------------
 template <typename T, typename TX>
-static void apply_inverse(hifde_factor_s& F, TX* X, int nrhs, hipStream_t st) {
+static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t st) {
   const int L = F.g.L;
   const size_t esz = sizeof(T), xsz = sizeof(TX);
-  int cap;
-  size_t smem;
   for (int l = 0; l < L; ++l) {
     CellLevel& C = F.cl[l];
     const CellStatic& S = *C.st;
-    solve_lds<T>(S.smax + 4, nrhs, &cap, &smem);
-    for (int color = 0; color < 2; ++color) {
-      const Work w = F.prof_mask ? cell_work(S, color, true, nrhs, esz, xsz) : Work{0, 0};
-      timed(F, HIFDE_PROF_CELL_UP, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_cell_up<T, TX>), dim3(S.ncell), dim3(kThreads), smem, st, X, nrhs,
-                           static_cast<const T*>(C.pool), S.fronts, S.idx, color, cap,
-                           static_cast<T*>(C.gscratch), C.gstride);
-      });
-    }
+    for (int color = 0; color < 2; ++color)
+      sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, S.sw, color, C.pk, C.dinv, S.idx, X, Z, nrhs, st);
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
-      solve_lds<T>(2 * G.ncskel + 4, nrhs, &cap, &smem);
-      const Work w = F.prof_mask ? group_work(G, true, nrhs, esz, xsz) : Work{0, 0};
-      timed(F, HIFDE_PROF_GROUP_UP, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_group_up<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X, nrhs,
-                           static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool), G.groups,
-                           G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+      const Work w = F.prof_mask ? interp_work(G, true, nrhs, esz, xsz) : Work{0, 0};
+      timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
+        hipLaunchKernelGGL((k_interp_up<T, TX>), dim3(G.nskel), dim3(kThreads), 0, st, G.groups,
+                           G.gsel, static_cast<const T*>(G.tpool), G.idx, X, nrhs);
       });
+      sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, G.sw, 0, G.pk, G.dinv, G.idx, X, Z, nrhs, st);
     }
   }
   CellLevel& top = F.cl[L];
-  solve_lds<double>(top.st->smax + 4, nrhs, &cap, &smem);
-  {
-    const Work w = F.prof_mask ? cell_work(*top.st, -1, true, nrhs, 8, xsz) : Work{0, 0};
-    timed(F, HIFDE_PROF_TOP, L, w.bytes, w.flops, st, [&] {
-      hipLaunchKernelGGL((k_cell_up<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st,
-                         X, nrhs, static_cast<const double*>(top.pool), top.st->fronts,
-                         top.st->idx, -1, cap, static_cast<double*>(top.gscratch), top.gstride);
-    });
-  }
-  {
-    const Work w = F.prof_mask ? cell_work(*top.st, -1, false, nrhs, 8, xsz) : Work{0, 0};
-    timed(F, HIFDE_PROF_TOP, L, w.bytes, w.flops, st, [&] {
-      hipLaunchKernelGGL((k_cell_down<double, TX>), dim3(top.st->ncell), dim3(kThreads), smem, st,
-                         X, nrhs, static_cast<const double*>(top.pool), top.st->fronts,
-                         top.st->idx, cap, static_cast<double*>(top.gscratch), top.gstride);
-    });
-  }
+  sweep_up<double, TX>(F, HIFDE_PROF_TOP, L, top.st->sw, 0, top.pk, top.dinv, top.st->idx, X, Z,
+                       nrhs, st);
+  sweep_down<double, TX>(F, HIFDE_PROF_TOP, L, top.st->sw, top.pk, top.st->idx, X, Z, nrhs, st);
   for (int l = L - 1; l >= 0; --l) {
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
-      solve_lds<T>(2 * G.ncskel + 4, nrhs, &cap, &smem);
-      const Work w = F.prof_mask ? group_work(G, false, nrhs, esz, xsz) : Work{0, 0};
-      timed(F, HIFDE_PROF_GROUP_DOWN, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_group_down<T, TX>), dim3(G.nskel), dim3(kThreads), smem, st, X,
-                           nrhs, static_cast<const T*>(G.fg), static_cast<const T*>(G.tpool),
-                           G.groups, G.gsel, G.idx, cap, static_cast<T*>(G.gscratch), G.gstride);
+      sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pk, G.idx, X, Z, nrhs, st);
+      const Work w = F.prof_mask ? interp_work(G, false, nrhs, esz, xsz) : Work{0, 0};
+      timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
+        hipLaunchKernelGGL((k_interp_down<T, TX>), dim3(G.nskel), dim3(kThreads), 0, st, G.groups,
+                           G.gsel, static_cast<const T*>(G.tpool), G.idx, X, nrhs);
       });
     }
     CellLevel& C = F.cl[l];
-    solve_lds<T>(C.st->smax + 4, nrhs, &cap, &smem);
-    const Work w = F.prof_mask ? cell_work(*C.st, -1, false, nrhs, esz, xsz) : Work{0, 0};
-    timed(F, HIFDE_PROF_CELL_DOWN, l, w.bytes, w.flops, st, [&] {
-      hipLaunchKernelGGL((k_cell_down<T, TX>), dim3(C.st->ncell), dim3(kThreads), smem, st, X,
-                         nrhs, static_cast<const T*>(C.pool), C.st->fronts, C.st->idx, cap,
-                         static_cast<T*>(C.gscratch), C.gstride);
-    });
+    sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, C.st->sw, C.pk, C.st->idx, X, Z, nrhs, st);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -882,6 +965,7 @@ static void apply_inverse(hifde_factor_s& F, TX* X, int nrhs, hipStream_t st) {
 static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
   const size_t need = size_t(F.g.N) * size_t(nrhs) * 8;
   if (F.X.bytes < need) F.X.alloc(need);
+  if (F.Z.bytes < need) F.Z.alloc(need);
 }
 
 // z = F^-1 r for double unknown-major vectors.
@@ -891,11 +975,12 @@ static void precond(hifde_factor_s& F, const double* r, double* z, int nrhs, hip
     ensure_X(F, nrhs);
     float* Xf = F.X.as<float>();
     hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(kThreads), 0, st, n, r, Xf);
-    apply_inverse<float, float>(F, Xf, nrhs, st);
+    apply_inverse<float, float>(F, Xf, F.Z.as<float>(), nrhs, st);
     hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n)), dim3(kThreads), 0, st, n, Xf, z);
   } else {
+    ensure_X(F, nrhs);
     if (z != r) HIP_CHECK(hipMemcpyAsync(z, r, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
-    apply_inverse<double, double>(F, z, nrhs, st);
+    apply_inverse<double, double>(F, z, F.Z.as<double>(), nrhs, st);
   }
 }
 
@@ -1091,14 +1176,14 @@ int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, do
       float* X = F->X.as<float>();
       hipLaunchKernelGGL(k_from_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
                          f, ldf, X);
-      apply_inverse<float, float>(*F, X, int(nrhs), st);
+      apply_inverse<float, float>(*F, X, F->Z.as<float>(), int(nrhs), st);
       hipLaunchKernelGGL(k_to_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
                          X, u, ldu);
     } else {
       double* X = F->X.as<double>();
       hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N,
                          int(nrhs), f, ldf, X);
-      apply_inverse<double, double>(*F, X, int(nrhs), st);
+      apply_inverse<double, double>(*F, X, F->Z.as<double>(), int(nrhs), st);
       hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N,
                          int(nrhs), X, u, ldu);
     }
