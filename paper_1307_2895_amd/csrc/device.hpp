@@ -46,13 +46,30 @@ struct FrontDev {
 };
 
 // A front as the F^-1 sweeps see it: packed apply-form tiles at element
-// `off` of the packed pool, D^-1 at `dv`, unknown list at `idx`.
+// `off` of the up pool and `offt` of the down (transposed) pool, D^-1 at
+// `dv`, unknown list at `idx`.
 struct PackDev {
   int64_t off;
+  int64_t offt;
   int64_t dv;
   int64_t idx;
   int32_t s, p;
 };
+
+// Tiles before row tile ti of a packed front with P16 = ceil(p/16) column
+// tiles: row tile t holds min(t + 1, P16) tiles.
+__host__ __device__ inline int64_t packed_before(int ti, int P16) {
+  if (ti <= P16) return int64_t(ti) * (ti + 1) / 2;
+  return int64_t(P16) * (P16 + 1) / 2 + int64_t(ti - P16) * P16;
+}
+__host__ __device__ inline int64_t packed_tiles(int s, int p) {
+  return packed_before((s + 15) >> 4, (p + 15) >> 4);
+}
+// Same for the transposed copy: row tile tc (< ceil(p/16)) holds the
+// rt - tc tiles of column tiles tc .. rt - 1.
+__host__ __device__ inline int64_t packed_before_t(int tc, int rt) {
+  return int64_t(tc) * rt - int64_t(tc) * (tc - 1) / 2;
+}
 
 // A skeletonization group.
 struct GroupDev {

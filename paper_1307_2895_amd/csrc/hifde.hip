@@ -11,6 +11,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hifde.h"
@@ -105,7 +106,7 @@ struct Arena {
 struct SweepSet {
   std::vector<PackDev> ph;
   std::vector<int2> up_h[2], down_h;
-  int64_t pk_elems = 0, dv_elems = 0;
+  int64_t pk_elems = 0, pt_elems = 0, dv_elems = 0;
   int kup = 0, kdown = 0;            // rows of x one work-group stages at most
   double fac[2] = {0, 0}, srows[2] = {0, 0}, prows[2] = {0, 0};
   PackDev* packs = nullptr;
@@ -118,11 +119,13 @@ static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool color
   for (const FrontDev& f : fh) {
     PackDev q{};
     q.off = S.pk_elems;
+    q.offt = S.pt_elems;
     q.dv = S.dv_elems;
     q.idx = f.idx;
     q.s = f.s;
     q.p = f.p;
     S.pk_elems += packed_tiles(f.s, f.p) * 256;
+    S.pt_elems += packed_tiles(f.s, f.p) * 256;
     S.dv_elems += f.p;
     const int fi = int(S.ph.size());
     S.ph.push_back(q);
@@ -191,7 +194,7 @@ struct CellLevel {
   std::shared_ptr<CellStatic> st;
   void* pool = nullptr;              // frontal matrices
   int* info = nullptr;
-  void *pk = nullptr, *dinv = nullptr;  // packed apply form, D^-1
+  void *pk = nullptr, *pt = nullptr, *dinv = nullptr;  // packed apply form (up, down), D^-1
 };
 
 struct GroupLevel {
@@ -207,7 +210,7 @@ struct GroupLevel {
   int64_t perm_stride = 0;
   int nskel = 0, ngroup = 0, ncskel = 0;
   SweepSet sw;                       // F^-1 sweeps over the skeleton fronts
-  void *pk = nullptr, *dinv = nullptr;
+  void *pk = nullptr, *pt = nullptr, *dinv = nullptr;
   // interpolation work: elements kr, rows r and k
   double tel = 0, rrows = 0, krows = 0;
 };
@@ -488,13 +491,18 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
 // Packed apply form and D^-1 of every front (the sweeps' copy).
 template <typename T>
 static void pack_fronts(Arena& mem, const T* pool, const std::vector<FrontDev>& fh,
-                        const FrontDev* fronts_d, const SweepSet& S, void** pk, void** dinv,
-                        hipStream_t st) {
+                        const FrontDev* fronts_d, const SweepSet& S, void** pk, void** pt,
+                        void** dinv, hipStream_t st) {
   *pk = mem.get<T>(size_t(std::max<int64_t>(S.pk_elems, 1)));
+  *pt = mem.get<T>(size_t(std::max<int64_t>(S.pt_elems, 1)));
   *dinv = mem.get<T>(size_t(std::max<int64_t>(S.dv_elems, 1)));
   if (fh.empty()) return;
-  hipLaunchKernelGGL(k_pack<T>, dim3(unsigned(fh.size())), dim3(kThreads), 0, st, pool, fronts_d,
-                     S.packs, static_cast<T*>(*pk), static_cast<T*>(*dinv));
+  int smax = 0;
+  for (const FrontDev& f : fh) smax = std::max(smax, f.s);
+  const unsigned rtmax = unsigned((smax + 15) / 16);
+  if (rtmax > 65535) throw Error(HIFDE_EINVAL, "front too large for the packing grid");
+  hipLaunchKernelGGL(k_pack<T>, dim3(unsigned(fh.size()), std::max(1u, rtmax)), dim3(kThreads), 0, st, pool, fronts_d,
+                     S.packs, static_cast<T*>(*pk), static_cast<T*>(*pt), static_cast<T*>(*dinv));
   HIP_CHECK(hipGetLastError());
 }
 
@@ -550,7 +558,8 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   HIP_CHECK(hipGetLastError());
   batched_ldl<T>(static_cast<T*>(D.pool), S.fh, S.fronts, D.info, st);
   apply_form<T>(F.mem, static_cast<T*>(D.pool), S.fh, S.fronts, st);
-  pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.dinv, st);
+  pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
+                 &D.dinv, st);
 }
 
 static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
@@ -688,7 +697,8 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   apply_form<T>(F.mem, static_cast<T*>(G.fg), G.ff, G.fgfronts, st);
   build_sweep(G.sw, G.ff, false);
   upload_sweep(G.sw, F.mem, st);
-  pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.dinv, st);
+  pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.pt,
+                 &G.dinv, st);
 }
 
 template <typename T>
@@ -877,45 +887,39 @@ static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, i
   const Work w = F.prof_mask ? sweep_work(S, c, true, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
   const T* P = static_cast<const T*>(pk);
   const T* Dv = static_cast<const T*>(dinv);
+  const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
   timed(F, cls, level, w.bytes, w.flops, st, [&] {
-    switch (g.NT) {
-      case 1:
-        hipLaunchKernelGGL((k_sweep_up<T, TX, 1>), dim3(g.grid), dim3(kThreads), g.lds, st,
-                           S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_sweep_up<T, TX, 2>), dim3(g.grid), dim3(kThreads), g.lds, st,
-                           S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch);
-        break;
-      default:
-        hipLaunchKernelGGL((k_sweep_up<T, TX, 4>), dim3(g.grid), dim3(kThreads), g.lds, st,
-                           S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch);
+#define HIFDE_UP(NTV, VV)                                                                       \
+  hipLaunchKernelGGL((k_sweep_up<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,       \
+                     S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch)
+    if (vec) {
+      if (g.NT == 1) HIFDE_UP(1, true); else if (g.NT == 2) HIFDE_UP(2, true); else HIFDE_UP(4, true);
+    } else {
+      if (g.NT == 1) HIFDE_UP(1, false); else if (g.NT == 2) HIFDE_UP(2, false); else HIFDE_UP(4, false);
     }
+#undef HIFDE_UP
   });
 }
 
 template <typename T, typename TX>
-static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S, const void* pk,
+static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S, const void* pt,
                        const int32_t* idx, TX* X, const TX* Z, int nrhs, hipStream_t st) {
   const int n = int(S.down_h.size());
   if (n == 0) return;
   const SweepShape g = sweep_shape<T>(n, nrhs, S.kdown);
   const Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
-  const T* P = static_cast<const T*>(pk);
+  const T* P = static_cast<const T*>(pt);
+  const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
   timed(F, cls, level, w.bytes, w.flops, st, [&] {
-    switch (g.NT) {
-      case 1:
-        hipLaunchKernelGGL((k_sweep_down<T, TX, 1>), dim3(g.grid), dim3(kThreads), g.lds, st,
-                           S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_sweep_down<T, TX, 2>), dim3(g.grid), dim3(kThreads), g.lds, st,
-                           S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch);
-        break;
-      default:
-        hipLaunchKernelGGL((k_sweep_down<T, TX, 4>), dim3(g.grid), dim3(kThreads), g.lds, st,
-                           S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch);
+#define HIFDE_DN(NTV, VV)                                                                       \
+  hipLaunchKernelGGL((k_sweep_down<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,     \
+                     S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch)
+    if (vec) {
+      if (g.NT == 1) HIFDE_DN(1, true); else if (g.NT == 2) HIFDE_DN(2, true); else HIFDE_DN(4, true);
+    } else {
+      if (g.NT == 1) HIFDE_DN(1, false); else if (g.NT == 2) HIFDE_DN(2, false); else HIFDE_DN(4, false);
     }
+#undef HIFDE_DN
   });
 }
 
@@ -945,11 +949,11 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
   CellLevel& top = F.cl[L];
   sweep_up<double, TX>(F, HIFDE_PROF_TOP, L, top.st->sw, 0, top.pk, top.dinv, top.st->idx, X, Z,
                        nrhs, st);
-  sweep_down<double, TX>(F, HIFDE_PROF_TOP, L, top.st->sw, top.pk, top.st->idx, X, Z, nrhs, st);
+  sweep_down<double, TX>(F, HIFDE_PROF_TOP, L, top.st->sw, top.pt, top.st->idx, X, Z, nrhs, st);
   for (int l = L - 1; l >= 0; --l) {
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
-      sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pk, G.idx, X, Z, nrhs, st);
+      sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pt, G.idx, X, Z, nrhs, st);
       const Work w = F.prof_mask ? interp_work(G, false, nrhs, esz, xsz) : Work{0, 0};
       timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
         hipLaunchKernelGGL((k_interp_down<T, TX>), dim3(G.nskel), dim3(kThreads), 0, st, G.groups,
@@ -957,7 +961,7 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
       });
     }
     CellLevel& C = F.cl[l];
-    sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, C.st->sw, C.pk, C.st->idx, X, Z, nrhs, st);
+    sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, C.st->sw, C.pt, C.st->idx, X, Z, nrhs, st);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -968,20 +972,126 @@ static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
   if (F.Z.bytes < need) F.Z.alloc(need);
 }
 
-// z = F^-1 r for double unknown-major vectors.
-static void precond(hifde_factor_s& F, const double* r, double* z, int nrhs, hipStream_t st) {
-  const int64_t n = F.g.N * int64_t(nrhs);
-  if (F.prec == HIFDE_MIXED) {
-    ensure_X(F, nrhs);
-    float* Xf = F.X.as<float>();
-    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(kThreads), 0, st, n, r, Xf);
-    apply_inverse<float, float>(F, Xf, F.Z.as<float>(), nrhs, st);
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n)), dim3(kThreads), 0, st, n, Xf, z);
-  } else {
-    ensure_X(F, nrhs);
-    if (z != r) HIP_CHECK(hipMemcpyAsync(z, r, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
-    apply_inverse<double, double>(F, z, F.Z.as<double>(), nrhs, st);
+
+// Conjugate gradients preconditioned by F^-1 (Section 5), one independent
+// iteration per column, all vectors unknown-major in double; TR is the type
+// of the preconditioner's vectors (float: flexible beta).  Returns whether
+// every column reached tol.
+template <typename TR>
+static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
+                    int64_t ldu, double tol, int maxit, int* iters, double* relres,
+                    hipStream_t st) {
+  const int64_t N = F.g.N, n = N * nrhs;
+  const int nr = int(nrhs);
+  const int flexible = sizeof(TR) == 4 ? 1 : 0;
+  // vectors: x r p Ap zold (double), partials, scalars
+  const size_t vbytes = size_t(n) * 8;
+  const size_t pbytes = size_t(kPcgBlocks) * 2 * nr * 8;
+  if (F.pcg_rhs != nrhs) {
+    F.pcg.alloc(vbytes * 5 + pbytes + size_t(nr) * 8 * 8 + size_t(nr) * 4);
+    F.pcg_rhs = nrhs;
   }
+  ensure_X(F, nrhs);
+  TR* rc = F.X.as<TR>();          // r copy, turned into z by the sweeps
+  TR* Zs = F.Z.as<TR>();
+  char* base = F.pcg.as<char>();
+  double* x = reinterpret_cast<double*>(base);
+  double* r = x + n;
+  double* p = r + n;
+  double* Ap = p + n;
+  double* zold = Ap + n;
+  double* partial = zold + n;
+  double* sc = partial + size_t(kPcgBlocks) * 2 * nr;
+  double* rz = sc;
+  double* alpha = sc + nr;
+  double* beta = sc + 2 * nr;
+  double* d1 = sc + 3 * nr;
+  int* live = reinterpret_cast<int*>(sc + 8 * nr);
+  const unsigned nb = kPcgBlocks;
+  const int dim = F.g.dim;
+  const int64_t side = F.g.n;
+  const double* diag = F.diag.as<double>();
+  const double* offd = F.offd.as<double>();
+
+  hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
+                     r);
+  HIP_CHECK(hipMemsetAsync(x, 0, vbytes, st));
+  HIP_CHECK(hipMemsetAsync(p, 0, vbytes, st));
+  HIP_CHECK(hipMemsetAsync(alpha, 0, size_t(nr) * 8, st));
+  // ||f||^2 and the preconditioner's copy of r
+  hipLaunchKernelGGL((k_pcg_xr<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, alpha, p, Ap, x, r,
+                     rc, partial);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, partial, d1);
+  std::vector<int> liveh(nr, 1), itsh(nr, 0);
+  std::vector<double> fh(nr), h1(nr);
+  HIP_CHECK(hipMemcpyAsync(fh.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int c = 0; c < nr; ++c) {
+    fh[c] = std::sqrt(fh[c]);
+    if (fh[c] == 0.0) liveh[c] = 0;
+  }
+  HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
+  apply_inverse<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs, nr,
+                                                                                      st);
+  HIP_CHECK(hipMemsetAsync(zold, 0, vbytes, st));
+  hipLaunchKernelGGL((k_pcg_z<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, zold, 0, partial);
+  HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
+  hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz, live,
+                     beta);
+  hipLaunchKernelGGL(k_pcg_p, dim3(nblk(n)), dim3(kThreads), 0, st, n, nr, beta, live, zold, p);
+  int it = 0;
+  while (it < maxit) {
+    bool any = false;
+    for (int c = 0; c < nr; ++c) any = any || liveh[c];
+    if (!any) break;
+    ++it;
+    hipLaunchKernelGGL(k_pcg_ap, dim3(nb), dim3(kThreads), 0, st, N, nr, dim, side, diag, offd, p,
+                       Ap, partial);
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz,
+                       live, alpha);
+    hipLaunchKernelGGL((k_pcg_xr<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, alpha, p, Ap, x, r,
+                       rc, partial);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, partial, d1);
+    HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    bool changed = false, anyl = false;
+    for (int c = 0; c < nr; ++c) {
+      if (!liveh[c]) continue;
+      itsh[c] = it;
+      if (std::sqrt(h1[c]) <= tol * fh[c]) {
+        liveh[c] = 0;
+        changed = true;
+      }
+      anyl = anyl || liveh[c];
+    }
+    if (changed) HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
+    if (!anyl || it == maxit) break;
+    apply_inverse<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs,
+                                                                                        nr, st);
+    hipLaunchKernelGGL((k_pcg_z<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, zold,
+                       flexible, partial);
+    hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz,
+                       live, beta);
+    hipLaunchKernelGGL(k_pcg_p, dim3(nblk(n)), dim3(kThreads), 0, st, n, nr, beta, live, zold, p);
+  }
+  // true residuals ||f - A x||
+  hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, dim, side, diag, offd,
+                     x, Ap);
+  hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
+                     r);
+  hipLaunchKernelGGL(k_pcg_resid, dim3(nb), dim3(kThreads), 0, st, N, nr, r, Ap, partial);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, partial, d1);
+  HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, x, u, ldu);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));
+  bool converged = true;
+  for (int c = 0; c < nr; ++c) {
+    iters[c] = itsh[c];
+    relres[c] = fh[c] > 0 ? std::sqrt(h1[c]) / fh[c] : 0.0;
+    if (liveh[c]) converged = false;
+  }
+  return converged;
 }
 
 }  // namespace hifde
@@ -1223,115 +1333,10 @@ int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, doub
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   bool converged = true;
   int rc = guarded([&] {
-    const int64_t N = F->g.N, n = N * nrhs;
-    const int nr = int(nrhs);
-    const bool flexible = F->prec == HIFDE_MIXED;
-    // vectors: x r z p Ap zold dz (unknown-major, double)
-    const int nvec = 7;
-    const size_t vbytes = size_t(n) * 8;
-    if (F->pcg_rhs != nrhs) {
-      F->pcg.alloc(vbytes * nvec + size_t(kDotBlocks) * 3 * nr * 8 + size_t(nr) * 8 * 12 +
-                   size_t(nr) * 4);
-      F->pcg_rhs = nrhs;
-    }
-    char* base = F->pcg.as<char>();
-    double* x = reinterpret_cast<double*>(base);
-    double* r = x + n;
-    double* z = r + n;
-    double* p = z + n;
-    double* Ap = p + n;
-    double* zold = Ap + n;
-    double* dz = zold + n;
-    double* partial = dz + n;
-    double* sc = partial + size_t(kDotBlocks) * 3 * nr;  // scalars
-    double* rz = sc;
-    double* pap = sc + nr;
-    double* alpha = sc + 2 * nr;
-    double* beta = sc + 3 * nr;
-    double* d3 = sc + 4 * nr;   // 3 x nr dot results
-    double* ff = sc + 7 * nr;   // ||f||^2
-    int* live = reinterpret_cast<int*>(sc + 12 * nr);
-    auto dots = [&](int np, const double* a0, const double* b0, const double* a1, const double* b1,
-                    const double* a2, const double* b2, double* outp) {
-      hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, st, N, nr, np, a0, b0,
-                         a1, b1, a2, b2, partial);
-      hipLaunchKernelGGL(k_dot_final, dim3(np * nr), dim3(kThreads), 0, st, kDotBlocks, nr, np,
-                         partial, outp);
-    };
-    hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
-                       r);
-    HIP_CHECK(hipMemsetAsync(x, 0, vbytes, st));
-    std::vector<int> liveh(nr, 1), itsh(nr, 0);
-    std::vector<double> h3(3 * nr), fh(nr);
-    dots(1, r, r, nullptr, nullptr, nullptr, nullptr, ff);
-    HIP_CHECK(hipMemcpyAsync(fh.data(), ff, nr * 8, hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    for (int c = 0; c < nr; ++c) {
-      fh[c] = std::sqrt(fh[c]);
-      if (fh[c] == 0.0) liveh[c] = 0;
-    }
-    HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
-    precond(*F, r, z, nr, st);
-    HIP_CHECK(hipMemcpyAsync(p, z, vbytes, hipMemcpyDeviceToDevice, st));
-    if (flexible) HIP_CHECK(hipMemcpyAsync(zold, z, vbytes, hipMemcpyDeviceToDevice, st));
-    dots(1, r, z, nullptr, nullptr, nullptr, nullptr, rz);
-    int it = 0;
-    while (it < maxit) {
-      bool any = false;
-      for (int c = 0; c < nr; ++c) any = any || liveh[c];
-      if (!any) break;
-      ++it;
-      hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, F->g.dim, F->g.n,
-                         F->diag.as<double>(), F->offd.as<double>(), p, Ap);
-      dots(1, p, Ap, nullptr, nullptr, nullptr, nullptr, pap);
-      hipLaunchKernelGGL(k_pcg_alpha, dim3(nblk(nr)), dim3(kThreads), 0, st, nr, rz, pap, live, alpha);
-      hipLaunchKernelGGL(k_pcg_update_xr, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, alpha, p, Ap,
-                         x, r);
-      dots(1, r, r, nullptr, nullptr, nullptr, nullptr, d3);
-      HIP_CHECK(hipMemcpyAsync(h3.data(), d3, nr * 8, hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipStreamSynchronize(st));
-      bool changed = false;
-      for (int c = 0; c < nr; ++c) {
-        if (!liveh[c]) continue;
-        itsh[c] = it;
-        if (std::sqrt(h3[c]) <= tol * fh[c]) {
-          liveh[c] = 0;
-          changed = true;
-        }
-      }
-      if (changed) HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
-      bool anyl = false;
-      for (int c = 0; c < nr; ++c) anyl = anyl || liveh[c];
-      if (!anyl || it == maxit) break;
-      precond(*F, r, z, nr, st);
-      if (flexible) {
-        hipLaunchKernelGGL(k_sub_and_copy, dim3(nblk(n)), dim3(kThreads), 0, st, n, z, zold, dz);
-        dots(2, r, dz, r, z, nullptr, nullptr, d3);
-      } else {
-        dots(2, r, z, r, z, nullptr, nullptr, d3);
-      }
-      hipLaunchKernelGGL(k_pcg_beta, dim3(nblk(nr)), dim3(kThreads), 0, st, nr, d3, d3 + nr, rz,
-                         live, beta);
-      hipLaunchKernelGGL(k_pcg_update_p, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, beta, live, z,
-                         p);
-    }
-    // true residuals
-    hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, F->g.dim, F->g.n,
-                       F->diag.as<double>(), F->offd.as<double>(), x, Ap);
-    hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
-                       r);
-    hipLaunchKernelGGL(k_sub_and_copy, dim3(nblk(n)), dim3(kThreads), 0, st, n, r, Ap, dz);
-    dots(1, dz, dz, nullptr, nullptr, nullptr, nullptr, d3);
-    HIP_CHECK(hipMemcpyAsync(h3.data(), d3, nr * 8, hipMemcpyDeviceToHost, st));
-    hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, x, u,
-                       ldu);
-    HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipStreamSynchronize(st));
-    for (int c = 0; c < nr; ++c) {
-      iters[c] = itsh[c];
-      relres[c] = fh[c] > 0 ? std::sqrt(h3[c]) / fh[c] : 0.0;
-      if (liveh[c]) converged = false;
-    }
+    if (F->prec == HIFDE_MIXED)
+      converged = run_pcg<float>(*F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
+    else
+      converged = run_pcg<double>(*F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
   });
   if (rc != HIFDE_OK) return rc;
   if (!converged) return fail(HIFDE_ENOCONV, "PCG did not reach the tolerance within maxit");
