@@ -58,7 +58,11 @@ typedef enum {
 } hifde_precision;
 
 enum {
-  HIFDE_DEBUG_DETERMINISM = 4u  /* factor every level twice, compare bitwise */
+  HIFDE_DEBUG_DETERMINISM = 4u, /* factor every level twice, compare bitwise */
+  HIFDE_NO_GRAPH = 16u          /* apply F^-1 by direct kernel launches; by
+                                   default the launches of one application
+                                   are captured once per right-hand-side
+                                   count into a HIP graph and replayed      */
 };
 
 /* Maximum number of tree levels reported by hifde_stats. */

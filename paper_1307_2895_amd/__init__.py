@@ -12,7 +12,8 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (  # noqa: F401
-    HIFDE_FP64, HIFDE_MIXED, HifdeError, Prof, Sets, Stats, check, lib,
+    HIFDE_FP64, HIFDE_MIXED, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH,
+    HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
     HIFDE_PROF_CLASSES,

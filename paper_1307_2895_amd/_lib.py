@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhifde.so")
 HIFDE_OK, HIFDE_EINVAL, HIFDE_ENOMEM, HIFDE_EDEVICE, HIFDE_ENOTSPD, HIFDE_ENOCONV, HIFDE_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
 HIFDE_FP64, HIFDE_MIXED = 0, 1
+HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH = 4, 16
 HIFDE_MAX_LEVELS = 24
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD",

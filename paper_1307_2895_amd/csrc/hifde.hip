@@ -253,7 +253,15 @@ struct hifde_factor_s {
   std::vector<ProfEvent> prof_ev;
   size_t prof_used = 0;
   hifde_prof_t prof_acc[HIFDE_PROF_CLASSES]{};
+  // captured F^-1 application (one per right-hand-side count and buffers)
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_nrhs = 0;
+  const void *g_x = nullptr, *g_z = nullptr;
   ~hifde_factor_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
     for (ProfEvent& e : prof_ev) {
       if (e.a) (void)hipEventDestroy(e.a);
       if (e.b) (void)hipEventDestroy(e.b);
@@ -618,6 +626,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.gw = F.mem.get<T>(size_t(S.gw_elems));
   HIP_CHECK(hipMemsetAsync(G.gw, 0, size_t(S.gw_elems) * sizeof(T), st));
   G.tpool = F.mem.get<T>(size_t(S.t_elems));
+  HIP_CHECK(hipMemsetAsync(G.tpool, 0, size_t(S.t_elems) * sizeof(T), st));
   G.groups = F.mem.upload(G.gh, st);
   PoolTable pt_cur{{F.cl[l].pool, nullptr, nullptr}};
   hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
@@ -966,6 +975,45 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
   HIP_CHECK(hipGetLastError());
 }
 
+// F^-1 application through a HIP graph: the launches of one application
+// (fixed buffers, fixed right-hand-side count) are captured once on a
+// private stream and replayed on the caller's stream.  Timed launches
+// (hifde_profile) and HIFDE_NO_GRAPH use direct launches.
+template <typename T, typename TX>
+static void apply_inverse_g(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t st) {
+  if (!F.use_graph || F.prof_mask) {
+    apply_inverse<T, TX>(F, X, Z, nrhs, st);
+    return;
+  }
+  if (!(F.gexec && F.g_nrhs == nrhs && F.g_x == X && F.g_z == Z)) {
+    if (F.gexec) {
+      HIP_CHECK(hipGraphExecDestroy(F.gexec));
+      F.gexec = nullptr;
+    }
+    if (!F.cap) HIP_CHECK(hipStreamCreateWithFlags(&F.cap, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamBeginCapture(F.cap, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      apply_inverse<T, TX>(F, X, Z, nrhs, F.cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(F.cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIP_CHECK(hipStreamEndCapture(F.cap, &g));
+    hipError_t e = hipGraphInstantiate(&F.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      F.gexec = nullptr;
+      HIP_CHECK(e);
+    }
+    F.g_nrhs = nrhs;
+    F.g_x = X;
+    F.g_z = Z;
+  }
+  HIP_CHECK(hipGraphLaunch(F.gexec, st));
+}
+
 static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
   const size_t need = size_t(F.g.N) * size_t(nrhs) * 8;
   if (F.X.bytes < need) F.X.alloc(need);
@@ -1031,8 +1079,8 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
     if (fh[c] == 0.0) liveh[c] = 0;
   }
   HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
-  apply_inverse<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs, nr,
-                                                                                      st);
+  apply_inverse_g<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs,
+                                                                                        nr, st);
   HIP_CHECK(hipMemsetAsync(zold, 0, vbytes, st));
   hipLaunchKernelGGL((k_pcg_z<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, zold, 0, partial);
   HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
@@ -1066,8 +1114,8 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
     }
     if (changed) HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
     if (!anyl || it == maxit) break;
-    apply_inverse<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs,
-                                                                                        nr, st);
+    apply_inverse_g<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs,
+                                                                                          nr, st);
     hipLaunchKernelGGL((k_pcg_z<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, zold,
                        flexible, partial);
     hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz,
@@ -1092,6 +1140,83 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
     if (liveh[c]) converged = false;
   }
   return converged;
+}
+
+// Stencil assembly and the factorization of every level into F.
+static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* const* a,
+                         const double* b, double eps, hifde_precision prec, hipStream_t st) {
+  F.g = tree->g;
+  F.prec = prec;
+  F.eps = eps;
+  F.planner.reset(new Planner(F.g));
+  F.cl.resize(F.g.L + 1);
+  F.gl.resize(F.g.L);
+  const int64_t N = F.g.N;
+  F.diag.alloc(size_t(N) * 8);
+  F.offd.alloc(size_t(N) * F.g.dim * 8);
+  const double** aptr = F.mem.get<const double*>(F.g.dim);
+  int* bad = F.mem.get<int>(1);
+  std::vector<const double*> ah(a, a + F.g.dim);
+  HIP_CHECK(hipMemcpyAsync(aptr, ah.data(), ah.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_stencil, dim3(nblk(N)), dim3(kThreads), 0, st, aptr, F.g.dim, F.g.n, N, b,
+                     F.diag.as<double>(), F.offd.as<double>(), bad);
+  HIP_CHECK(hipGetLastError());
+  int badh = 0;
+  HIP_CHECK(hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (badh & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
+  if (badh & 2) throw Error(HIFDE_EINVAL, "b must be finite");
+  if (prec == HIFDE_MIXED) run_factor<float>(F, tree, st);
+  else run_factor<double>(F, tree, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// Counts the bytes that differ between two device buffers.
+__global__ void k_count_diff(int64_t n, const unsigned char* a, const unsigned char* b,
+                             unsigned long long* cnt) {
+  unsigned long long c = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    c += a[i] != b[i] ? 1ull : 0ull;
+  if (c) atomicAdd(cnt, c);
+}
+
+// HIFDE_DEBUG_DETERMINISM: the skeleton choices and every stored value of
+// two factorizations of the same input must agree bit for bit.
+static void compare_factors(hifde_factor_s& A, hifde_factor_s& B, hipStream_t st) {
+  DevMem cnt;
+  cnt.alloc(8);
+  unsigned long long* c = cnt.as<unsigned long long>();
+  auto same = [&](const void* x, const void* y, size_t bytes, const char* what, int l) {
+    if (bytes == 0) return;
+    HIP_CHECK(hipMemsetAsync(c, 0, 8, st));
+    hipLaunchKernelGGL(k_count_diff, dim3(1024), dim3(kThreads), 0, st, int64_t(bytes),
+                       static_cast<const unsigned char*>(x), static_cast<const unsigned char*>(y), c);
+    unsigned long long h = 0;
+    HIP_CHECK(hipMemcpyAsync(&h, c, 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (h) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "nondeterministic factorization: %llu bytes of %s differ at level %d",
+               h, what, l);
+      throw Error(HIFDE_EDEVICE, buf);
+    }
+  };
+  const int L = A.g.L;
+  for (int l = 0; l <= L; ++l) {
+    const size_t esz = (l == L || A.prec == HIFDE_FP64) ? 8 : 4;
+    const SweepSet& S = A.cl[l].st->sw;
+    same(A.cl[l].pk, B.cl[l].pk, size_t(S.pk_elems) * esz, "cell factors", l);
+    same(A.cl[l].dinv, B.cl[l].dinv, size_t(S.dv_elems) * esz, "cell pivots", l);
+    if (l == L) continue;
+    const GroupLevel& GA = A.gl[l];
+    const GroupLevel& GB = B.gl[l];
+    if (GA.nskel != GB.nskel || GA.gsel_h != GB.gsel_h || GA.idx_h != GB.idx_h)
+      throw Error(HIFDE_EDEVICE, "nondeterministic skeleton choice at level " + std::to_string(l));
+    same(GA.pk, GB.pk, size_t(GA.sw.pk_elems) * esz, "skeleton-front factors", l);
+    same(GA.tpool, GB.tpool, size_t(GA.st->t_elems) * esz, "interpolation matrices", l);
+  }
 }
 
 }  // namespace hifde
@@ -1122,46 +1247,29 @@ void hifde_factor_free(hifde_factor_t F) { delete F; }
 
 int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, double eps,
                  hifde_precision prec, uint32_t flags, void* hip_stream, hifde_factor_t* out) {
-  (void)flags;
   if (!out) return fail(HIFDE_EINVAL, "out is NULL");
   *out = nullptr;
   if (!tree || !a) return fail(HIFDE_EINVAL, "tree or a is NULL");
   if (!(eps >= 0.0 && eps < 1.0)) return fail(HIFDE_EINVAL, "eps must lie in [0, 1)");
   if (prec != HIFDE_FP64 && prec != HIFDE_MIXED) return fail(HIFDE_EINVAL, "unknown precision");
+  if (flags & ~uint32_t(HIFDE_DEBUG_DETERMINISM | HIFDE_NO_GRAPH))
+    return fail(HIFDE_EINVAL, "unknown flags");
   for (int k = 0; k < tree->g.dim; ++k)
     if (!a[k]) return fail(HIFDE_EINVAL, "a[k] is NULL");
   std::unique_ptr<hifde_factor_s> F(new hifde_factor_s);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int rc = guarded([&] {
     auto t0 = std::chrono::steady_clock::now();
-    F->g = tree->g;
-    F->prec = prec;
-    F->eps = eps;
-    F->planner.reset(new Planner(F->g));
-    F->cl.resize(F->g.L + 1);
-    F->gl.resize(F->g.L);
-    const int64_t N = F->g.N;
-    F->diag.alloc(size_t(N) * 8);
-    F->offd.alloc(size_t(N) * F->g.dim * 8);
-    const double** aptr = F->mem.get<const double*>(F->g.dim);
-    int* bad = F->mem.get<int>(1);
-    std::vector<const double*> ah(a, a + F->g.dim);
-    HIP_CHECK(hipMemcpyAsync(aptr, ah.data(), ah.size() * sizeof(void*), hipMemcpyHostToDevice, st));
-    HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_stencil, dim3(nblk(N)), dim3(kThreads), 0, st, aptr, F->g.dim, F->g.n, N, b,
-                       F->diag.as<double>(), F->offd.as<double>(), bad);
-    HIP_CHECK(hipGetLastError());
-    int badh = 0;
-    HIP_CHECK(hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    if (badh & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
-    if (badh & 2) throw Error(HIFDE_EINVAL, "b must be finite");
-    if (prec == HIFDE_MIXED) run_factor<float>(*F, tree, st);
-    else run_factor<double>(*F, tree, st);
-    HIP_CHECK(hipStreamSynchronize(st));
+    build_factor(*F, tree, a, b, eps, prec, st);
+    F->use_graph = !(flags & HIFDE_NO_GRAPH);
     fill_stats(*F);
     F->stats.factor_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (flags & HIFDE_DEBUG_DETERMINISM) {
+      hifde_factor_s F2;
+      build_factor(F2, tree, a, b, eps, prec, st);
+      compare_factors(*F, F2, st);
+    }
   });
   if (rc == HIFDE_OK) *out = F.release();
   return rc;
@@ -1286,14 +1394,14 @@ int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, do
       float* X = F->X.as<float>();
       hipLaunchKernelGGL(k_from_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
                          f, ldf, X);
-      apply_inverse<float, float>(*F, X, F->Z.as<float>(), int(nrhs), st);
+      apply_inverse_g<float, float>(*F, X, F->Z.as<float>(), int(nrhs), st);
       hipLaunchKernelGGL(k_to_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
                          X, u, ldu);
     } else {
       double* X = F->X.as<double>();
       hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N,
                          int(nrhs), f, ldf, X);
-      apply_inverse<double, double>(*F, X, F->Z.as<double>(), int(nrhs), st);
+      apply_inverse_g<double, double>(*F, X, F->Z.as<double>(), int(nrhs), st);
       hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N,
                          int(nrhs), X, u, ldu);
     }

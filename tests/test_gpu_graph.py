@@ -1,0 +1,76 @@
+"""GPU: the captured (HIP graph) application of F^-1 against direct
+launches, and the determinism check of the factorization.
+
+The sweeps are deterministic (no atomics, fixed reduction orders), so a
+replayed graph must reproduce the direct launches bit for bit; every replay
+is checked, with eager work and synchronizations between replays.
+"""
+import numpy as np
+import pytest
+
+from synth import workloads as W
+
+from _helpers import torch_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nrhs", [1, 16, 40])
+def test_graph_replays_match_direct_launches(prec, nrhs):
+    import paper_1307_2895_amd as H
+    print(f"case prec={prec} nrhs={nrhs}", flush=True)
+    dim, n, m = 2, 64, 8
+    a = W.make_field(dim, n, "bernoulli_contrast", 3)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    Fg = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+    Fd = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec, flags=H.HIFDE_NO_GRAPH)
+    f = torch.from_numpy(W.make_rhs(n ** dim, nrhs, 5)).cuda()
+    ud = H.hifde_solve(Fd, f)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        ug = H.hifde_solve(Fg, f)
+        torch.cuda.synchronize()
+        assert torch.equal(ug, ud), f"replay {rep} differs"
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+    # a different right-hand-side count recaptures
+    f2 = f[:, :1].contiguous()
+    assert torch.equal(H.hifde_solve(Fg, f2), H.hifde_solve(Fd, f2))
+
+
+def test_graph_pcg_matches_direct():
+    import paper_1307_2895_amd as H
+    dim, n, m = 2, 64, 8
+    a = W.make_field(dim, n, "loguniform", 4)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    Fg = H.hifde_factor(T, torch_inputs(a), None, 1e-6, H.HIFDE_MIXED)
+    Fd = H.hifde_factor(T, torch_inputs(a), None, 1e-6, H.HIFDE_MIXED, flags=H.HIFDE_NO_GRAPH)
+    f = torch.from_numpy(W.make_rhs(n ** dim, 8, 6)).cuda()
+    ug, itg, rg = H.hifde_pcg(Fg, f, tol=1e-12)
+    ud, itd, rd = H.hifde_pcg(Fd, f, tol=1e-12)
+    assert np.array_equal(itg, itd)
+    assert torch.equal(ug, ud)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_debug_determinism_flag(prec):
+    import paper_1307_2895_amd as H
+    dim, n, m = 3, 16, 4
+    a = W.make_field(dim, n, "lognormal_grf", 4)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    F = H.hifde_factor(T, torch_inputs(a), None, 1e-4, prec, flags=H.HIFDE_DEBUG_DETERMINISM)
+    assert H.hifde_stats(F)["top_size"] > 0
+
+
+def test_unknown_flags_rejected():
+    import paper_1307_2895_amd as H
+    a = W.make_field(2, 32, "const", None)
+    T = H.hifde_build_tree(2, 32, 4, 0)
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_factor(T, torch_inputs(a), None, 1e-6, 0, flags=1 << 20)
+    assert ei.value.code == H.HIFDE_EINVAL
