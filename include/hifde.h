@@ -178,6 +178,55 @@ int hifde_profile(hifde_factor_t F, uint32_t class_mask, int level);
  * and clears the class's counters. */
 int hifde_profile_read(hifde_factor_t F, int cls, hifde_prof_t* out);
 
+/* ---- Skeleton-rank predictor ------------------------------------------
+ * A 3-layer tanh perceptron HIFDE_RANK_FEATURES -> 64 -> 64 -> 1 (float)
+ * predicts log2(1 + k), k the skeleton count of a group at level l+1/2,
+ * from the group's features (level, |c|, |c^N|, eps, dimension and the
+ * statistics of log10 a on the stencil links at c and at c^N).  With
+ * HIFDE_USE_RANK_MODEL, hifde_factor sizes and launches the skeleton-front
+ * eliminations of a level from the predicted ranks before the IDs'
+ * results reach the host; the tolerance-driven IDs still decide every
+ * skeleton, and a front whose actual rank leaves the launched bound is
+ * eliminated again after the IDs return (counted in hifde_stats).
+ * Parameters (HIFDE_RANK_PARAMS floats): W1 (64 x F, row-major), b1 (64),
+ * W2 (64 x 64), b2 (64), W3 (1 x 64), b3 (1).  All pointers of the hifde_mlp
+ * calls are DEVICE pointers; work is ordered on hip_stream. */
+#define HIFDE_RANK_FEATURES 16
+#define HIFDE_RANK_HIDDEN 64
+#define HIFDE_RANK_PARAMS (64 * 16 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* Bytes of device workspace hifde_mlp_grad needs for nbatch samples. */
+int hifde_mlp_workspace(int64_t nbatch, int64_t* bytes);
+
+/* out[b] = network(feat[b, :]) for nbatch samples (feat row-major). */
+int hifde_mlp_forward(const float* params, int64_t nbatch, const float* feat,
+                      float* out, void* hip_stream);
+
+/* Gradient of the mean squared error (1/B) sum_b (out[b] - target[b])^2
+ * with respect to params into grad (HIFDE_RANK_PARAMS floats) and the loss
+ * into *loss (one float, device).  Sums over the batch run in a fixed
+ * order.  work: hifde_mlp_workspace(nbatch) bytes. */
+int hifde_mlp_grad(const float* params, int64_t nbatch, const float* feat,
+                   const float* target, float* grad, float* loss, void* work,
+                   void* hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, epsilon 1e-8, bias-corrected;
+ * step counts from 1) on params with moments m, v. */
+int hifde_mlp_adam(float* params, const float* grad, float* m, float* v,
+                   int64_t step, float lr, void* hip_stream);
+
+/* Features of the groups of level `level` + 1/2 of a factorization into
+ * feat (DEVICE, cap x HIFDE_RANK_FEATURES) and, when target is not NULL,
+ * the log2(1 + k) of the skeleton counts the factorization chose (DEVICE,
+ * cap): training data drawn from the method itself.  *ngroups (HOST) gets
+ * the number of groups; feat = NULL only reports it. */
+int hifde_rank_features(hifde_factor_t F, int level, float* feat, float* target,
+                        int64_t cap, int64_t* ngroups, void* hip_stream);
+
+/* Weights (HOST, HIFDE_RANK_PARAMS floats) used by later hifde_factor calls
+ * on this tree with HIFDE_USE_RANK_MODEL; NULL removes the model. */
+int hifde_set_rank_model(hifde_tree_t tree, const float* weights, int64_t nweights);
+
 /* Statistics of a factor (HOST out). */
 int hifde_stats(hifde_factor_t F, hifde_stats_t* out);
 

@@ -16,7 +16,7 @@ from ._lib import (  # noqa: F401
     HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
-    HIFDE_PROF_CLASSES,
+    HIFDE_PROF_CLASSES, HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN, HIFDE_RANK_PARAMS,
 )
 
 
@@ -193,3 +193,69 @@ def hifde_plan_replay(tree: Tree, redundant_level) -> Factor:
     h = C.c_void_p()
     check(lib().hifde_plan_replay(tree._h, rl.ctypes.data_as(C.c_void_p), C.byref(h)))
     return Factor(h, tree)
+
+
+# ---- skeleton-rank predictor -------------------------------------------
+
+def _f32(t, shape=None):
+    if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float32"):
+        raise HifdeError(-1, "expected a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise HifdeError(-1, f"expected shape {shape}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def hifde_mlp_forward(params, feat, stream=None):
+    """Network outputs (log2(1 + k) predictions) for feat (B x 16)."""
+    import torch
+    B = feat.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=feat.device)
+    check(lib().hifde_mlp_forward(_f32(params, (HIFDE_RANK_PARAMS,)), B,
+                                  _f32(feat, (B, HIFDE_RANK_FEATURES)), _f32(out),
+                                  _stream(stream)))
+    return out
+
+
+def hifde_mlp_grad(params, feat, target, stream=None):
+    """(gradient of the mean squared error, loss tensor of one float)."""
+    import torch
+    B = feat.shape[0]
+    nb = C.c_int64()
+    check(lib().hifde_mlp_workspace(B, C.byref(nb)))
+    work = torch.empty(nb.value // 4, dtype=torch.float32, device=feat.device)
+    g = torch.empty(HIFDE_RANK_PARAMS, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    check(lib().hifde_mlp_grad(_f32(params, (HIFDE_RANK_PARAMS,)), B,
+                               _f32(feat, (B, HIFDE_RANK_FEATURES)), _f32(target, (B,)),
+                               _f32(g), _f32(loss), _f32(work), _stream(stream)))
+    return g, loss
+
+
+def hifde_mlp_adam(params, grad, m, v, step: int, lr: float, stream=None):
+    """One Adam step in place on params (m, v: moment tensors)."""
+    check(lib().hifde_mlp_adam(_f32(params), _f32(grad), _f32(m), _f32(v), int(step),
+                               float(lr), _stream(stream)))
+
+
+def hifde_rank_features(F: Factor, level: int, stream=None):
+    """(features B x 16, targets log2(1 + k)) of the groups of level + 1/2."""
+    import torch
+    ng = C.c_int64()
+    check(lib().hifde_rank_features(F._h, int(level), None, None, 0, C.byref(ng), None))
+    B = ng.value
+    feat = torch.zeros((max(B, 1), HIFDE_RANK_FEATURES), dtype=torch.float32, device="cuda")
+    tgt = torch.zeros(max(B, 1), dtype=torch.float32, device="cuda")
+    if B > 0:
+        check(lib().hifde_rank_features(F._h, int(level), _f32(feat), _f32(tgt), B,
+                                        C.byref(ng), _stream(stream)))
+    return feat[:B], tgt[:B]
+
+
+def hifde_set_rank_model(tree: Tree, weights):
+    """Rank-predictor weights (HIFDE_RANK_PARAMS floats, host) for later
+    factorizations of ``tree`` with HIFDE_USE_RANK_MODEL; None removes it."""
+    if weights is None:
+        check(lib().hifde_set_rank_model(tree._h, None, 0))
+        return
+    w = np.ascontiguousarray(weights, dtype=np.float32).ravel()
+    check(lib().hifde_set_rank_model(tree._h, w.ctypes.data_as(C.c_void_p), w.size))

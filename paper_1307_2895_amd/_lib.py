@@ -27,8 +27,13 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD
 EXPORTED = [
     "hifde_build_tree", "hifde_factor", "hifde_solve", "hifde_pcg", "hifde_matvec",
     "hifde_stats", "hifde_export_sets", "hifde_plan_replay", "hifde_profile",
-    "hifde_profile_read", "hifde_tree_free", "hifde_factor_free", "hifde_last_error",
+    "hifde_profile_read", "hifde_mlp_workspace", "hifde_mlp_forward", "hifde_mlp_grad",
+    "hifde_mlp_adam", "hifde_rank_features", "hifde_set_rank_model", "hifde_tree_free",
+    "hifde_factor_free", "hifde_last_error",
 ]
+
+HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN = 16, 64
+HIFDE_RANK_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP = 0, 1, 2, 3
 HIFDE_PROF_CLASSES = 4
@@ -99,6 +104,12 @@ def lib():
     L.hifde_export_sets.argtypes = [vp, i32, C.POINTER(Sets)]
     L.hifde_plan_replay.argtypes = [vp, vp, C.POINTER(vp)]
     L.hifde_profile.argtypes = [vp, C.c_uint32, i32]
+    L.hifde_mlp_workspace.argtypes = [i64, C.POINTER(C.c_int64)]
+    L.hifde_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    L.hifde_mlp_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.hifde_mlp_adam.argtypes = [vp, vp, vp, vp, i64, C.c_float, vp]
+    L.hifde_rank_features.argtypes = [vp, i32, vp, vp, i64, C.POINTER(C.c_int64), vp]
+    L.hifde_set_rank_model.argtypes = [vp, vp, i64]
     L.hifde_profile_read.argtypes = [vp, i32, C.POINTER(Prof)]
     L.hifde_tree_free.argtypes = [vp]
     L.hifde_factor_free.argtypes = [vp]

@@ -20,6 +20,7 @@
 
 #include "kernels_factor.inc"
 #include "kernels_solve.inc"
+#include "kernels_mlp.inc"
 
 namespace hifde {
 
@@ -221,6 +222,8 @@ using namespace hifde;
 
 struct hifde_tree_s {
   Geom g;
+  std::vector<float> model;                 // rank predictor weights (host)
+  DevMem model_d;                           // and on the device
   std::shared_ptr<const LevelPlan> l0;      // level-0 cells and level-1/2 groups
   std::shared_ptr<CellStatic> c0;           // their device descriptions
   std::shared_ptr<GroupStatic> g0;
@@ -1219,6 +1222,29 @@ static void compare_factors(hifde_factor_s& A, hifde_factor_s& B, hipStream_t st
   }
 }
 
+// Device features of the groups of level l+1/2 (kRankF floats per group,
+// into feat) from the planned groups' [c^N; c] lists and the stencil.
+static void group_features(hifde_factor_s& F, int l, float* feat, hipStream_t st) {
+  const auto& groups = F.planner->level(l).groups();
+  if (groups.empty()) return;
+  std::vector<int32_t> lists, nn, nc;
+  std::vector<int64_t> offs;
+  for (const Group& g : groups) {
+    offs.push_back(int64_t(lists.size()));
+    lists.insert(lists.end(), g.cN.begin(), g.cN.end());
+    lists.insert(lists.end(), g.c.begin(), g.c.end());
+    nn.push_back(int32_t(g.cN.size()));
+    nc.push_back(int32_t(g.c.size()));
+  }
+  const int32_t* ld = F.mem.upload(lists, st);
+  const int64_t* od = F.mem.upload(offs, st);
+  const int32_t* nnd = F.mem.upload(nn, st);
+  const int32_t* ncd = F.mem.upload(nc, st);
+  hipLaunchKernelGGL(k_rank_features, dim3(unsigned(groups.size())), dim3(kThreads), 0, st, ld, od,
+                     nnd, ncd, F.offd.as<double>(), F.g.N, F.g.n, F.g.dim, F.eps, l, feat);
+  HIP_CHECK(hipGetLastError());
+}
+
 }  // namespace hifde
 
 // ===========================================================================
@@ -1330,6 +1356,95 @@ int hifde_profile_read(hifde_factor_t F, int cls, hifde_prof_t* out) {
     prof_collect(*F);
     *out = F->prof_acc[cls];
     F->prof_acc[cls] = hifde_prof_t{};
+  });
+}
+
+int hifde_mlp_workspace(int64_t nbatch, int64_t* bytes) {
+  if (!bytes || nbatch < 1) return fail(HIFDE_EINVAL, "bad arguments");
+  *bytes = (int64_t(4) * kRankH + 2) * 4 * nbatch;
+  return HIFDE_OK;
+}
+
+int hifde_mlp_forward(const float* params, int64_t nbatch, const float* feat, float* out,
+                      void* hip_stream) {
+  if (!params || !feat || !out || nbatch < 1) return fail(HIFDE_EINVAL, "bad arguments");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
+                       feat, out, static_cast<float*>(nullptr), static_cast<float*>(nullptr));
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+int hifde_mlp_grad(const float* params, int64_t nbatch, const float* feat, const float* target,
+                   float* grad, float* loss, void* work, void* hip_stream) {
+  if (!params || !feat || !target || !grad || !loss || !work || nbatch < 1)
+    return fail(HIFDE_EINVAL, "bad arguments");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    float* y = static_cast<float*>(work);
+    float* dy = y + nbatch;
+    float* h1 = dy + nbatch;
+    float* h2 = h1 + nbatch * kRankH;
+    float* dz1 = h2 + nbatch * kRankH;
+    float* dz2 = dz1 + nbatch * kRankH;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
+                       feat, y, h1, h2);
+    hipLaunchKernelGGL(k_mlp_backprop, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
+                       y, target, h1, h2, dy, dz1, dz2);
+    hipLaunchKernelGGL(k_mlp_param_grad, dim3(nblk(kRankP)), dim3(kThreads), 0, st, nbatch, feat,
+                       h1, h2, dy, dz1, dz2, grad);
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(kThreads), 0, st, nbatch, y, target, loss);
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+int hifde_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,
+                   void* hip_stream) {
+  if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f))
+    return fail(HIFDE_EINVAL, "bad arguments");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(kRankP)), dim3(kThreads), 0, st, params, grad, m, v,
+                       step, lr, 0.9f, 0.999f, 1e-8f);
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+int hifde_rank_features(hifde_factor_t F, int level, float* feat, float* target, int64_t cap,
+                        int64_t* ngroups, void* hip_stream) {
+  if (!F || !ngroups) return fail(HIFDE_EINVAL, "NULL argument");
+  if (F->plan_only) return fail(HIFDE_ESTATE, "factor holds no numerical data");
+  if (level < 0 || level >= F->g.L) return fail(HIFDE_EINVAL, "level out of range");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    const Level& lev = F->planner->level(level);
+    const int64_t ng = int64_t(lev.groups().size());
+    *ngroups = ng;
+    if (!feat) return;
+    if (cap < ng) throw Error(HIFDE_EINVAL, "cap is smaller than the number of groups");
+    group_features(*F, level, feat, st);
+    if (target) {
+      std::vector<float> t(ng);
+      for (int64_t g = 0; g < ng; ++g) t[g] = float(std::log2(1.0 + double(lev.res[g].k)));
+      HIP_CHECK(hipMemcpyAsync(target, t.data(), ng * 4, hipMemcpyHostToDevice, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+  });
+}
+
+int hifde_set_rank_model(hifde_tree_t tree, const float* weights, int64_t nweights) {
+  if (!tree) return fail(HIFDE_EINVAL, "NULL tree");
+  if (weights && nweights != kRankP) return fail(HIFDE_EINVAL, "nweights must be HIFDE_RANK_PARAMS");
+  return guarded([&] {
+    if (!weights) {
+      tree->model.clear();
+      tree->model_d.release();
+      return;
+    }
+    tree->model.assign(weights, weights + nweights);
+    tree->model_d.alloc(size_t(kRankP) * 4);
+    HIP_CHECK(hipMemcpy(tree->model_d.p, weights, size_t(kRankP) * 4, hipMemcpyHostToDevice));
   });
 }
 
