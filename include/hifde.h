@@ -58,11 +58,18 @@ typedef enum {
 } hifde_precision;
 
 enum {
+  HIFDE_USE_RANK_MODEL = 1u,    /* size and launch each level's skeleton-front
+                                   eliminations from the rank predictor's
+                                   output before the IDs return (needs
+                                   hifde_set_rank_model on the tree)        */
   HIFDE_DEBUG_DETERMINISM = 4u, /* factor every level twice, compare bitwise */
-  HIFDE_NO_GRAPH = 16u          /* apply F^-1 by direct kernel launches; by
+  HIFDE_NO_GRAPH = 16u,         /* apply F^-1 by direct kernel launches; by
                                    default the launches of one application
                                    are captured once per right-hand-side
                                    count into a HIP graph and replayed      */
+  HIFDE_PRESIZE_WORST_CASE = 64u /* as HIFDE_USE_RANK_MODEL with every rank
+                                   assumed 0 (the largest possible fronts):
+                                   the comparison point of the predictor    */
 };
 
 /* Maximum number of tree levels reported by hifde_stats. */
@@ -81,6 +88,12 @@ typedef struct {
   int64_t skel_in[HIFDE_MAX_LEVELS];  /* unknowns entering level l+1/2 groups  */
   int64_t skel_out[HIFDE_MAX_LEVELS]; /* skeletons kept at level l+1/2         */
   int32_t max_front[HIFDE_MAX_LEVELS];/* largest |p|+|c^N| of a level-l cell   */
+  int64_t rank_groups;              /* groups launched from predicted ranks   */
+  double rank_mae;                  /* mean |predicted - actual| of their k   */
+  int64_t rebuckets;                /* levels eliminated again because a rank
+                                       left the launched bound               */
+  int64_t skel_panels;              /* 32-pivot panel sweeps launched for the
+                                       skeleton fronts (all levels)          */
 } hifde_stats_t;
 
 /* Index sets of one (fractional) level, for comparison with other

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libhifde.so")
 HIFDE_OK, HIFDE_EINVAL, HIFDE_ENOMEM, HIFDE_EDEVICE, HIFDE_ENOTSPD, HIFDE_ENOCONV, HIFDE_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
 HIFDE_FP64, HIFDE_MIXED = 0, 1
-HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH = 4, 16
+HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH = 1, 4, 16
+HIFDE_PRESIZE_WORST_CASE = 64
 HIFDE_MAX_LEVELS = 24
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD",
@@ -60,6 +61,10 @@ class Stats(C.Structure):
         ("skel_in", C.c_int64 * HIFDE_MAX_LEVELS),
         ("skel_out", C.c_int64 * HIFDE_MAX_LEVELS),
         ("max_front", C.c_int32 * HIFDE_MAX_LEVELS),
+        ("rank_groups", C.c_int64),
+        ("rank_mae", C.c_double),
+        ("rebuckets", C.c_int64),
+        ("skel_panels", C.c_int64),
     ]
 
 

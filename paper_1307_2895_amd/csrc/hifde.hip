@@ -73,6 +73,28 @@ struct DevMem {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Page-locked host memory (asynchronous device-to-host copies).
+struct PinnedMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedMem() = default;
+  PinnedMem(const PinnedMem&) = delete;
+  PinnedMem& operator=(const PinnedMem&) = delete;
+  ~PinnedMem() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    release();
+    HIP_CHECK(hipHostMalloc(&p, b, hipHostMallocDefault));
+    bytes = b;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
 // Bump allocator for the device buffers of one factorization: a few large
 // hipMalloc calls instead of one per array, all released together.
 struct Arena {
@@ -115,7 +137,32 @@ struct SweepSet {
   int2* down = nullptr;
 };
 
-static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool colored) {
+// Work lists and per-color work of the fronts in S.ph (colors[i] per front).
+static void sweep_items(SweepSet& S, const std::vector<int>& colors) {
+  S.up_h[0].clear();
+  S.up_h[1].clear();
+  S.down_h.clear();
+  S.kup = S.kdown = 0;
+  for (int c = 0; c < 2; ++c) S.fac[c] = S.srows[c] = S.prows[c] = 0;
+  for (size_t fi = 0; fi < S.ph.size(); ++fi) {
+    const PackDev& f = S.ph[fi];
+    const int c = colors[fi];
+    const int rt = (f.s + 15) >> 4, P16 = (f.p + 15) >> 4;
+    for (int t = 0; t < rt; t += kSwWaves) {
+      S.up_h[c].push_back(make_int2(int(fi), t));
+      S.kup = std::max(S.kup, std::min(f.p, 16 * std::min(P16, std::min(rt, t + kSwWaves))));
+    }
+    for (int t = 0; t < P16; t += kSwWaves) S.down_h.push_back(make_int2(int(fi), t));
+    S.kdown = std::max(S.kdown, 16 * rt);
+    S.fac[c] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
+    S.srows[c] += f.s;
+    S.prows[c] += f.p;
+  }
+}
+
+// Packed layout of the fronts fh, back to back; with `worst`, every front
+// gets the slots of p = s (its pivot count is not known yet).
+static void sweep_layout(SweepSet& S, const std::vector<FrontDev>& fh, bool worst) {
   S = SweepSet{};
   for (const FrontDev& f : fh) {
     PackDev q{};
@@ -125,23 +172,20 @@ static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool color
     q.idx = f.idx;
     q.s = f.s;
     q.p = f.p;
-    S.pk_elems += packed_tiles(f.s, f.p) * 256;
-    S.pt_elems += packed_tiles(f.s, f.p) * 256;
-    S.dv_elems += f.p;
-    const int fi = int(S.ph.size());
+    const int pc = worst ? f.s : f.p;
+    S.pk_elems += packed_tiles(f.s, pc) * 256;
+    S.pt_elems += packed_tiles(f.s, pc) * 256;
+    S.dv_elems += pc;
     S.ph.push_back(q);
-    const int c = colored ? (f.color & 1) : 0;
-    const int rt = (f.s + 15) >> 4, P16 = (f.p + 15) >> 4;
-    for (int t = 0; t < rt; t += kSwWaves) {
-      S.up_h[c].push_back(make_int2(fi, t));
-      S.kup = std::max(S.kup, std::min(f.p, 16 * std::min(P16, std::min(rt, t + kSwWaves))));
-    }
-    for (int t = 0; t < P16; t += kSwWaves) S.down_h.push_back(make_int2(fi, t));
-    S.kdown = std::max(S.kdown, 16 * rt);
-    S.fac[c] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
-    S.srows[c] += f.s;
-    S.prows[c] += f.p;
   }
+}
+
+static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool colored) {
+  sweep_layout(S, fh, false);
+  std::vector<int> colors(fh.size(), 0);
+  if (colored)
+    for (size_t i = 0; i < fh.size(); ++i) colors[i] = fh[i].color & 1;
+  sweep_items(S, colors);
 }
 
 static void upload_sweep(SweepSet& S, Arena& mem, hipStream_t st) {
@@ -214,6 +258,10 @@ struct GroupLevel {
   void *pk = nullptr, *pt = nullptr, *dinv = nullptr;
   // interpolation work: elements kr, rows r and k
   double tel = 0, rrows = 0, krows = 0;
+  // predicted ranks (model) and the event that makes them readable
+  int32_t* khat_d = nullptr;
+  std::shared_ptr<PinnedMem> khat_h;
+  hipEvent_t pred_ev = nullptr;
 };
 
 }  // namespace hifde
@@ -256,13 +304,30 @@ struct hifde_factor_s {
   std::vector<ProfEvent> prof_ev;
   size_t prof_used = 0;
   hifde_prof_t prof_acc[HIFDE_PROF_CLASSES]{};
+  // skeleton-front launches before the IDs return: 0 = after (exact
+  // sizes), 1 = bounded by the rank model's predictions, 2 = worst case
+  int presize = 0;
+  hipStream_t aux = nullptr;               // rank-model inference
+  hipEvent_t offd_ev = nullptr;            // stencil ready (for aux)
+  const float* model = nullptr;            // device weights (tree-owned)
+  std::vector<hipEvent_t> events;          // created here, destroyed with F
+  int64_t rank_groups = 0, skel_panels = 0, rebuckets = 0;
+  double rank_abs_err = 0;
   // captured F^-1 application (one per right-hand-side count and buffers)
   bool use_graph = true;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_nrhs = 0;
   const void *g_x = nullptr, *g_z = nullptr;
+  hipEvent_t new_event() {
+    hipEvent_t e = nullptr;
+    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    events.push_back(e);
+    return e;
+  }
   ~hifde_factor_s() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamDestroy(aux);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap) (void)hipStreamDestroy(cap);
     for (ProfEvent& e : prof_ev) {
@@ -437,9 +502,12 @@ static void upload_group_static(GroupStatic& gs, hipStream_t st) {
 }
 
 // Batched partial LDL^T of a set of fronts already in `pool`.
+// With `bounds`, the p of fh are upper bounds of the device fronts' pivot
+// counts (the device holds the exact ones); launch shapes then cover any
+// count up to the bound.
 template <typename T>
 static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
-                        int* info_d, hipStream_t st) {
+                        int* info_d, hipStream_t st, bool bounds = false) {
   if (fh.empty()) return;
   int pmax = 0;
   for (const auto& f : fh) pmax = std::max(pmax, f.p);
@@ -448,7 +516,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     int64_t maxt = 0;
     for (const auto& f : fh) {
       if (j0 >= f.p) continue;
-      int r0 = std::min(j0 + kNB, f.p);
+      int r0 = bounds ? j0 + 1 : std::min(j0 + kNB, f.p);
       int64_t nt = f.s - r0;
       if (nt <= 0) continue;
       int64_t T_ = (nt + kTB - 1) / kTB;
@@ -468,7 +536,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
 // B = [L^-1; W^T L^-1] (mirrored into the upper trapezoid) and D by D^-1.
 template <typename T>
 static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
-                       const FrontDev* fronts_d, hipStream_t st) {
+                       const FrontDev* fronts_d, hipStream_t st, bool bounds = false) {
   if (fh.empty()) return;
   const unsigned nf = unsigned(fh.size());
   std::vector<int64_t> toff(fh.size());
@@ -485,7 +553,7 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
     int64_t tiles = 0;
     for (const auto& f : fh) {
       if (J >= f.p) continue;
-      const int nb = std::min(kNB, f.p - J);
+      const int nb = bounds ? 1 : std::min(kNB, f.p - J);
       tiles = std::max<int64_t>(tiles, (f.s - J - nb + kIR - 1) / kIR);
     }
     if (tiles > 0) {
@@ -590,6 +658,58 @@ static void check_info(const int* info, size_t n, const char* what, int l, hipSt
 // ---------------------------------------------------------------------------
 // Groups of level l+1/2: plan, base blocks, ID, skeleton fronts.
 // ---------------------------------------------------------------------------
+// Device features of the groups of level l+1/2 (kRankF floats per group,
+// into feat) from the planned groups' [c^N; c] lists and the stencil.
+static void group_features(hifde_factor_s& F, int l, float* feat, hipStream_t st) {
+  const auto& groups = F.planner->level(l).groups();
+  if (groups.empty()) return;
+  std::vector<int32_t> lists, nn, nc;
+  std::vector<int64_t> offs;
+  for (const Group& g : groups) {
+    offs.push_back(int64_t(lists.size()));
+    lists.insert(lists.end(), g.cN.begin(), g.cN.end());
+    lists.insert(lists.end(), g.c.begin(), g.c.end());
+    nn.push_back(int32_t(g.cN.size()));
+    nc.push_back(int32_t(g.c.size()));
+  }
+  const int32_t* ld = F.mem.upload(lists, st);
+  const int64_t* od = F.mem.upload(offs, st);
+  const int32_t* nnd = F.mem.upload(nn, st);
+  const int32_t* ncd = F.mem.upload(nc, st);
+  hipLaunchKernelGGL(k_rank_features, dim3(unsigned(groups.size())), dim3(kThreads), 0, st, ld, od,
+                     nnd, ncd, F.offd.as<double>(), F.g.N, F.g.n, F.g.dim, F.eps, l, feat);
+  HIP_CHECK(hipGetLastError());
+}
+
+// Rank-model inference for the groups of level l+1/2 on the auxiliary
+// stream (it overlaps the level's eliminations): features, network,
+// ranks, an asynchronous copy to page-locked memory and an event.
+static void predict_ranks(hifde_factor_s& F, GroupLevel& G, int l) {
+  const int ng = G.ngroup;
+  if (ng == 0) return;
+  if (!F.aux) {
+    HIP_CHECK(hipStreamCreateWithFlags(&F.aux, hipStreamNonBlocking));
+  }
+  HIP_CHECK(hipStreamWaitEvent(F.aux, F.offd_ev, 0));
+  float* feat = F.mem.get<float>(size_t(ng) * kRankF);
+  float* y = F.mem.get<float>(ng);
+  std::vector<int32_t> nc(ng);
+  for (int g = 0; g < ng; ++g) nc[g] = G.gh[g].nc;
+  const int32_t* ncd = F.mem.upload(nc, F.aux);
+  G.khat_d = F.mem.get<int32_t>(ng);
+  group_features(F, l, feat, F.aux);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(ng)), dim3(kThreads), 0, F.aux, F.model, int64_t(ng),
+                     feat, y, static_cast<float*>(nullptr), static_cast<float*>(nullptr));
+  hipLaunchKernelGGL(k_rank_from_output, dim3(nblk(ng)), dim3(kThreads), 0, F.aux, ng, y, ncd,
+                     G.khat_d);
+  G.khat_h = std::make_shared<PinnedMem>();
+  G.khat_h->ensure(size_t(ng) * 4);
+  HIP_CHECK(hipMemcpyAsync(G.khat_h->p, G.khat_d, size_t(ng) * 4, hipMemcpyDeviceToHost, F.aux));
+  G.pred_ev = F.new_event();
+  HIP_CHECK(hipEventRecord(G.pred_ev, F.aux));
+  HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
@@ -610,6 +730,8 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.ngroup = int(G.gh.size());
   const Level& lev = P.level(l);
   if (F.plan_only) return;
+  const bool pre = skel && F.presize != 0 && G.ngroup > 0;
+  if (pre && F.presize == 1) predict_ranks(F, G, l);
   upload_group_static(S, st);
   G.base = F.mem.get<T>(size_t(S.base_elems));
   HIP_CHECK(hipMemsetAsync(G.base, 0, size_t(S.base_elems) * sizeof(T), st));
@@ -630,6 +752,13 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   HIP_CHECK(hipMemsetAsync(G.gw, 0, size_t(S.gw_elems) * sizeof(T), st));
   G.tpool = F.mem.get<T>(size_t(S.t_elems));
   HIP_CHECK(hipMemsetAsync(G.tpool, 0, size_t(S.t_elems) * sizeof(T), st));
+  // with pre-launch every group owns a skeleton-front slot from the start
+  int64_t fg_all = 0;
+  if (pre)
+    for (GroupDev& d : G.gh) {
+      d.fg_off = fg_all;
+      fg_all += int64_t(d.nc) * d.nc;
+    }
   G.groups = F.mem.upload(G.gh, st);
   PoolTable pt_cur{{F.cl[l].pool, nullptr, nullptr}};
   hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
@@ -649,6 +778,54 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                      static_cast<T*>(G.tpool), G.groups, F.eps, tau, G.kout, G.perm,
                      G.perm_stride);
   HIP_CHECK(hipGetLastError());
+
+  // Pre-launch: the skeleton fronts of every group are formed, eliminated,
+  // turned into the apply form and packed before the ranks reach the host.
+  // The pivot count of each front comes from the IDs on the device; the
+  // host bounds the panel sweeps by the predicted (or worst-case) ranks.
+  std::vector<FrontDev> fall;
+  SweepSet sall;
+  std::vector<int32_t> khat;
+  int pbound = 0;
+  auto launch_fronts = [&](int bound) {
+    for (FrontDev& f : fall) f.p = std::min(f.s, bound);
+    G.fgfronts = F.mem.upload(fall, st);
+    upload_sweep(sall, F.mem, st);
+    hipLaunchKernelGGL(k_fix_fronts, dim3(nblk(G.ngroup)), dim3(kThreads), 0, st, G.ngroup, G.kout,
+                       G.fgfronts, sall.packs);
+    HIP_CHECK(hipMemsetAsync(G.fg, 0, size_t(fg_all) * sizeof(T), st));
+    HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ngroup, st));
+    hipLaunchKernelGGL(k_group_front<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
+                       static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
+                       static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
+                       G.perm, G.perm_stride, static_cast<const int32_t*>(nullptr), G.kout);
+    HIP_CHECK(hipGetLastError());
+    batched_ldl<T>(static_cast<T*>(G.fg), fall, G.fgfronts, G.info, st, true);
+    apply_form<T>(F.mem, static_cast<T*>(G.fg), fall, G.fgfronts, st, true);
+    F.skel_panels += (bound + kNB - 1) / kNB;
+    pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), fall, G.fgfronts, sall, &G.pk, &G.pt,
+                   &G.dinv, st);
+  };
+  if (pre) {
+    khat.assign(G.ngroup, 0);
+    if (F.presize == 1) {
+      HIP_CHECK(hipEventSynchronize(G.pred_ev));
+      std::copy(G.khat_h->as<int32_t>(), G.khat_h->as<int32_t>() + G.ngroup, khat.begin());
+    }
+    for (int gi = 0; gi < G.ngroup; ++gi) {
+      FrontDev f{};
+      f.off = G.gh[gi].fg_off;
+      f.s = G.gh[gi].nc;
+      fall.push_back(f);
+      pbound = std::max(pbound, G.gh[gi].nc - khat[gi]);
+    }
+    pbound = ((pbound + kNB - 1) / kNB) * kNB;   // whole panels
+    sweep_layout(sall, fall, true);
+    G.fg = F.mem.get<T>(size_t(std::max<int64_t>(fg_all, 1)));
+    G.info = F.mem.get<int>(G.ngroup);
+    launch_fronts(pbound);
+  }
+
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
   HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
@@ -662,20 +839,26 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.ff.clear();
   G.ncskel = 0;
   G.tel = G.rrows = G.krows = 0;
+  int rmax = 0;
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];
     if (k < 0 || k > d.nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
     P.set_skeleton(l, gi, k, ph.data() + size_t(gi) * ncmax);
+    if (pre) {
+      F.rank_groups += 1;
+      F.rank_abs_err += std::abs(double(khat[gi]) - double(k));
+    }
     d.k = k;
     d.skel = (k < d.nc) ? 1 : 0;
     if (!d.skel) continue;
-    d.fg_off = fg_off;
+    if (!pre) d.fg_off = fg_off;
     G.tel += double(k) * (d.nc - k);
     G.rrows += d.nc - k;
     G.krows += k;
+    rmax = std::max(rmax, d.nc - k);
     FrontDev f{};
-    f.off = fg_off;
+    f.off = d.fg_off;
     f.s = d.nc;
     f.p = d.nc - k;
     f.idx = int64_t(G.idx_h.size());
@@ -692,6 +875,33 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   tm.mark("  skeletons", l);
   G.nskel = int(G.gsel_h.size());
   G.groups = F.mem.upload(G.gh, st);
+  if (pre) {
+    // a rank beyond the launched panels: eliminate every front again with
+    // the actual bound (the IDs' choices are unchanged)
+    if (rmax > pbound) {
+      F.rebuckets += 1;
+      launch_fronts(((rmax + kNB - 1) / kNB) * kNB);
+    }
+    // the sweeps see the skeletonized groups, in their pre-launch slots
+    SweepSet& W = G.sw;
+    W = SweepSet{};
+    W.pk_elems = sall.pk_elems;
+    W.pt_elems = sall.pt_elems;
+    W.dv_elems = sall.dv_elems;
+    for (int gi : G.gsel_h) {
+      PackDev q = sall.ph[gi];
+      q.p = G.gh[gi].nc - G.gh[gi].k;
+      q.idx = G.gh[gi].idx;
+      W.ph.push_back(q);
+    }
+    sweep_items(W, std::vector<int>(W.ph.size(), 0));
+    upload_sweep(W, F.mem, st);
+    if (G.nskel > 0) {
+      G.idx = F.mem.upload(G.idx_h, st);
+      G.gsel = F.mem.upload(G.gsel_h, st);
+    }
+    return;
+  }
   if (G.nskel == 0) return;
   G.idx = F.mem.upload(G.idx_h, st);
   G.gsel = F.mem.upload(G.gsel_h, st);
@@ -703,10 +913,11 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   hipLaunchKernelGGL(k_group_front<T>, dim3(G.nskel), dim3(kThreads), 0, st,
                      static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
                      static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
-                     G.perm, G.perm_stride, G.gsel);
+                     G.perm, G.perm_stride, G.gsel, static_cast<const int32_t*>(nullptr));
   HIP_CHECK(hipGetLastError());
   batched_ldl<T>(static_cast<T*>(G.fg), G.ff, G.fgfronts, G.info, st);
   apply_form<T>(F.mem, static_cast<T*>(G.fg), G.ff, G.fgfronts, st);
+  F.skel_panels += (rmax + kNB - 1) / kNB;
   build_sweep(G.sw, G.ff, false);
   upload_sweep(G.sw, F.mem, st);
   pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.pt,
@@ -741,7 +952,10 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   // pivot checks of every level at once (one synchronization)
   for (int l = 0; l <= L; ++l) {
     check_info(F.cl[l].info, F.cl[l].st->fh.size(), l == L ? "top block" : "cell", l, st);
-    if (l < L && F.gl[l].nskel > 0) check_info(F.gl[l].info, size_t(F.gl[l].nskel), "group", l, st);
+    if (l < L && F.gl[l].info) {
+      const size_t ni = F.presize ? size_t(F.gl[l].ngroup) : size_t(F.gl[l].nskel);
+      if (ni > 0) check_info(F.gl[l].info, ni, "group", l, st);
+    }
   }
   tm.mark("pivot checks", L);
 }
@@ -796,6 +1010,10 @@ static void fill_stats(hifde_factor_s& F) {
   s.factor_flops = flops;
   s.solve_bytes = bytes;
   s.factor_bytes = mbytes;
+  s.rank_groups = F.rank_groups;
+  s.rank_mae = F.rank_groups > 0 ? F.rank_abs_err / double(F.rank_groups) : 0.0;
+  s.rebuckets = F.rebuckets;
+  s.skel_panels = F.skel_panels;
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,6 +1383,10 @@ static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* co
   hipLaunchKernelGGL(k_stencil, dim3(nblk(N)), dim3(kThreads), 0, st, aptr, F.g.dim, F.g.n, N, b,
                      F.diag.as<double>(), F.offd.as<double>(), bad);
   HIP_CHECK(hipGetLastError());
+  if (F.presize == 1) {
+    F.offd_ev = F.new_event();
+    HIP_CHECK(hipEventRecord(F.offd_ev, st));
+  }
   int badh = 0;
   HIP_CHECK(hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
@@ -1222,28 +1444,6 @@ static void compare_factors(hifde_factor_s& A, hifde_factor_s& B, hipStream_t st
   }
 }
 
-// Device features of the groups of level l+1/2 (kRankF floats per group,
-// into feat) from the planned groups' [c^N; c] lists and the stencil.
-static void group_features(hifde_factor_s& F, int l, float* feat, hipStream_t st) {
-  const auto& groups = F.planner->level(l).groups();
-  if (groups.empty()) return;
-  std::vector<int32_t> lists, nn, nc;
-  std::vector<int64_t> offs;
-  for (const Group& g : groups) {
-    offs.push_back(int64_t(lists.size()));
-    lists.insert(lists.end(), g.cN.begin(), g.cN.end());
-    lists.insert(lists.end(), g.c.begin(), g.c.end());
-    nn.push_back(int32_t(g.cN.size()));
-    nc.push_back(int32_t(g.c.size()));
-  }
-  const int32_t* ld = F.mem.upload(lists, st);
-  const int64_t* od = F.mem.upload(offs, st);
-  const int32_t* nnd = F.mem.upload(nn, st);
-  const int32_t* ncd = F.mem.upload(nc, st);
-  hipLaunchKernelGGL(k_rank_features, dim3(unsigned(groups.size())), dim3(kThreads), 0, st, ld, od,
-                     nnd, ncd, F.offd.as<double>(), F.g.N, F.g.n, F.g.dim, F.eps, l, feat);
-  HIP_CHECK(hipGetLastError());
-}
 
 }  // namespace hifde
 
@@ -1278,14 +1478,22 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
   if (!tree || !a) return fail(HIFDE_EINVAL, "tree or a is NULL");
   if (!(eps >= 0.0 && eps < 1.0)) return fail(HIFDE_EINVAL, "eps must lie in [0, 1)");
   if (prec != HIFDE_FP64 && prec != HIFDE_MIXED) return fail(HIFDE_EINVAL, "unknown precision");
-  if (flags & ~uint32_t(HIFDE_DEBUG_DETERMINISM | HIFDE_NO_GRAPH))
+  if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_NO_GRAPH |
+                        HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "unknown flags");
+  if ((flags & HIFDE_USE_RANK_MODEL) && (flags & HIFDE_PRESIZE_WORST_CASE))
+    return fail(HIFDE_EINVAL, "HIFDE_USE_RANK_MODEL and HIFDE_PRESIZE_WORST_CASE exclude each other");
+  if ((flags & HIFDE_USE_RANK_MODEL) && tree && tree->model.empty())
+    return fail(HIFDE_ESTATE, "HIFDE_USE_RANK_MODEL without a rank model on the tree");
   for (int k = 0; k < tree->g.dim; ++k)
     if (!a[k]) return fail(HIFDE_EINVAL, "a[k] is NULL");
   std::unique_ptr<hifde_factor_s> F(new hifde_factor_s);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int rc = guarded([&] {
     auto t0 = std::chrono::steady_clock::now();
+    const int presize = (flags & HIFDE_USE_RANK_MODEL) ? 1 : (flags & HIFDE_PRESIZE_WORST_CASE) ? 2 : 0;
+    F->presize = presize;
+    F->model = presize == 1 ? tree->model_d.as<float>() : nullptr;
     build_factor(*F, tree, a, b, eps, prec, st);
     F->use_graph = !(flags & HIFDE_NO_GRAPH);
     fill_stats(*F);
@@ -1293,6 +1501,8 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (flags & HIFDE_DEBUG_DETERMINISM) {
       hifde_factor_s F2;
+      F2.presize = presize;
+      F2.model = F->model;
       build_factor(F2, tree, a, b, eps, prec, st);
       compare_factors(*F, F2, st);
     }
