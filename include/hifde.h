@@ -63,6 +63,13 @@ enum {
                                    output before the IDs return (needs
                                    hifde_set_rank_model on the tree)        */
   HIFDE_DEBUG_DETERMINISM = 4u, /* factor every level twice, compare bitwise */
+  HIFDE_AUTOTUNE = 8u,          /* time every launch variant of each unseen
+                                   size bucket (trailing-update tiles of the
+                                   LDL^T on FMA or matrix cores; ID grid or
+                                   persistent queue) on a snapshot of its
+                                   data and keep the fastest in the tree;
+                                   later factorizations of the tree reuse
+                                   the choices with or without this flag   */
   HIFDE_NO_GRAPH = 16u,         /* apply F^-1 by direct kernel launches; by
                                    default the launches of one application
                                    are captured once per right-hand-side
@@ -94,6 +101,7 @@ typedef struct {
                                        left the launched bound               */
   int64_t skel_panels;              /* 32-pivot panel sweeps launched for the
                                        skeleton fronts (all levels)          */
+  int64_t tuned;                    /* size buckets the autotuner timed      */
 } hifde_stats_t;
 
 /* Index sets of one (fractional) level, for comparison with other

@@ -13,6 +13,7 @@ import numpy as np
 
 from ._lib import (  # noqa: F401
     HIFDE_FP64, HIFDE_MIXED, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH, HIFDE_USE_RANK_MODEL,
+    HIFDE_AUTOTUNE,
     HIFDE_PRESIZE_WORST_CASE,
     HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
@@ -151,7 +152,7 @@ def hifde_stats(F: Factor) -> dict:
         "skel_in": list(s.skel_in[:L]), "skel_out": list(s.skel_out[:L]),
         "max_front": list(s.max_front[:L + 1]),
         "rank_groups": s.rank_groups, "rank_mae": s.rank_mae, "rebuckets": s.rebuckets,
-        "skel_panels": s.skel_panels,
+        "skel_panels": s.skel_panels, "tuned": s.tuned,
     }
 
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhifde.so")
 HIFDE_OK, HIFDE_EINVAL, HIFDE_ENOMEM, HIFDE_EDEVICE, HIFDE_ENOTSPD, HIFDE_ENOCONV, HIFDE_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
 HIFDE_FP64, HIFDE_MIXED = 0, 1
-HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH = 1, 4, 16
+HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_AUTOTUNE, HIFDE_NO_GRAPH = 1, 4, 8, 16
 HIFDE_PRESIZE_WORST_CASE = 64
 HIFDE_MAX_LEVELS = 24
 
@@ -65,6 +65,7 @@ class Stats(C.Structure):
         ("rank_mae", C.c_double),
         ("rebuckets", C.c_int64),
         ("skel_panels", C.c_int64),
+        ("tuned", C.c_int64),
     ]
 
 

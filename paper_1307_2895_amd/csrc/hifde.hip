@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -270,6 +271,7 @@ using namespace hifde;
 
 struct hifde_tree_s {
   Geom g;
+  std::map<uint64_t, int> tune;             // autotuner choices (see tune_choice)
   std::vector<float> model;                 // rank predictor weights (host)
   DevMem model_d;                           // and on the device
   std::shared_ptr<const LevelPlan> l0;      // level-0 cells and level-1/2 groups
@@ -312,6 +314,9 @@ struct hifde_factor_s {
   const float* model = nullptr;            // device weights (tree-owned)
   std::vector<hipEvent_t> events;          // created here, destroyed with F
   int64_t rank_groups = 0, skel_panels = 0, rebuckets = 0;
+  bool autotune = false;                   // HIFDE_AUTOTUNE
+  hifde_tree_s* tree = nullptr;            // owner of the tuning cache
+  int64_t tuned = 0;
   double rank_abs_err = 0;
   // captured F^-1 application (one per right-hand-side count and buffers)
   bool use_graph = true;
@@ -502,17 +507,32 @@ static void upload_group_static(GroupStatic& gs, hipStream_t st) {
 }
 
 // Batched partial LDL^T of a set of fronts already in `pool`.
+// Fronts with more than j pivots: all of them, or (fh sorted by p,
+// descending) the leading ones only.
+static unsigned active_fronts(const std::vector<FrontDev>& fh, int j, bool sorted) {
+  if (!sorted) return unsigned(fh.size());
+  unsigned n = 0;
+  while (n < fh.size() && fh[n].p > j) ++n;
+  return n;
+}
+
+// Trailing-update variants of the batched LDL^T.
+enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_VARIANTS = 2 };
+
 // With `bounds`, the p of fh are upper bounds of the device fronts' pivot
 // counts (the device holds the exact ones); launch shapes then cover any
-// count up to the bound.
+// count up to the bound.  With `sorted` (fh by p, descending), the launches
+// of panel j cover only the fronts that still have pivots there.
 template <typename T>
 static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
-                        int* info_d, hipStream_t st, bool bounds = false) {
+                        int* info_d, hipStream_t st, bool bounds = false, bool sorted = false,
+                        int variant = LDL_MFMA) {
   if (fh.empty()) return;
   int pmax = 0;
   for (const auto& f : fh) pmax = std::max(pmax, f.p);
-  const unsigned nf = unsigned(fh.size());
   for (int j0 = 0; j0 < pmax; j0 += kNB) {
+    const unsigned nf = active_fronts(fh, j0, sorted);
+    if (nf == 0) break;
     int64_t maxt = 0;
     for (const auto& f : fh) {
       if (j0 >= f.p) continue;
@@ -525,20 +545,22 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     hipLaunchKernelGGL(k_ldl_panel<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, j0, info_d);
     if (maxt > 0) {
       if (maxt > 65535) throw Error(HIFDE_EINVAL, "front too large for the trailing-update grid");
-      hipLaunchKernelGGL(k_ldl_update<T>, dim3(nf, unsigned(maxt)), dim3(kThreads), 0, st, pool,
-                         fronts_d, j0);
+      if (variant == LDL_MFMA)
+        hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(nf, unsigned(maxt)), dim3(kThreads), 0, st,
+                           pool, fronts_d, j0);
+      else
+        hipLaunchKernelGGL(k_ldl_update<T>, dim3(nf, unsigned(maxt)), dim3(kThreads), 0, st, pool,
+                           fronts_d, j0);
     }
   }
   HIP_CHECK(hipGetLastError());
 }
 
-// Replace each partially factored front's [L; W^T] by its apply form
-// B = [L^-1; W^T L^-1] (mirrored into the upper trapezoid) and D by D^-1.
 template <typename T>
 static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
-                       const FrontDev* fronts_d, hipStream_t st, bool bounds = false) {
+                       const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
+                       bool sorted = false) {
   if (fh.empty()) return;
-  const unsigned nf = unsigned(fh.size());
   std::vector<int64_t> toff(fh.size());
   int64_t tot = 0;
   int pmax = 0;
@@ -556,12 +578,14 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
       const int nb = bounds ? 1 : std::min(kNB, f.p - J);
       tiles = std::max<int64_t>(tiles, (f.s - J - nb + kIR - 1) / kIR);
     }
+    const unsigned na = active_fronts(fh, J, sorted);
+    if (na == 0) continue;
     if (tiles > 0) {
       if (tiles > 65535) throw Error(HIFDE_EINVAL, "front too large for the inversion grid");
-      hipLaunchKernelGGL(k_inv_step<T>, dim3(nf, unsigned(tiles)), dim3(kThreads), 0, st, pool,
+      hipLaunchKernelGGL(k_inv_step<T>, dim3(na, unsigned(tiles)), dim3(kThreads), 0, st, pool,
                          fronts_d, J, tmp, toff_d);
     }
-    hipLaunchKernelGGL(k_inv_commit<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
+    hipLaunchKernelGGL(k_inv_commit<T>, dim3(na), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
                        toff_d);
   }
   HIP_CHECK(hipGetLastError());
@@ -605,6 +629,81 @@ static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
 // ---------------------------------------------------------------------------
 // Cells of level l: plan, assemble, factor.
 // ---------------------------------------------------------------------------
+// Autotuner: the variant of a launch family for a size bucket.  Without
+// HIFDE_AUTOTUNE the tree's cached choice (or the default) is used; with it,
+// an unseen bucket runs every variant once on a snapshot of the data it
+// modifies (buf, bytes), timed with events, keeps the fastest for the tree,
+// and restores the data for the real run.
+enum { FAM_LDL = 1, FAM_CPQR = 2 };
+static uint64_t tune_key(int fam, int esz, int a, int b, int c) {
+  auto bucket = [](int v) {
+    int k = 0;
+    while ((1 << k) < v) ++k;
+    return uint64_t(k);
+  };
+  return (uint64_t(fam) << 56) | (uint64_t(esz) << 48) | (bucket(a) << 32) | (bucket(b) << 16) |
+         bucket(c);
+}
+
+// HIFDE_TUNE_FORCE="ldl=<v>,cpqr=<v>" pins a family's variant (testing).
+static int forced_variant(int fam) {
+  const char* e = getenv("HIFDE_TUNE_FORCE");
+  if (!e) return -1;
+  const std::string s(e), name = fam == FAM_LDL ? "ldl=" : "cpqr=";
+  const size_t at = s.find(name);
+  if (at == std::string::npos) return -1;
+  return std::atoi(s.c_str() + at + name.size());
+}
+
+template <class Run>
+static int tune_choice(hifde_factor_s& F, uint64_t key, int nvar, int dflt, void* buf,
+                       size_t bytes, hipStream_t st, Run run) {
+  const int forced = forced_variant(int(key >> 56));
+  if (forced >= 0 && forced < nvar) return forced;
+  hifde_tree_s* tree = F.tree;
+  if (tree) {
+    auto it = tree->tune.find(key);
+    if (it != tree->tune.end()) return it->second;
+  }
+  if (!F.autotune || !tree || bytes == 0) return dflt;
+  DevMem save;
+  save.alloc(bytes);
+  HIP_CHECK(hipMemcpyAsync(save.p, buf, bytes, hipMemcpyDeviceToDevice, st));
+  hipEvent_t a = nullptr, b = nullptr;   // timing events, destroyed with F
+  HIP_CHECK(hipEventCreate(&a));
+  F.events.push_back(a);
+  HIP_CHECK(hipEventCreate(&b));
+  F.events.push_back(b);
+  float best = 0.f;
+  int bi = dflt;
+  for (int v = 0; v < nvar; ++v) {
+    if (v > 0) HIP_CHECK(hipMemcpyAsync(buf, save.p, bytes, hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipEventRecord(a, st));
+    run(v);
+    HIP_CHECK(hipEventRecord(b, st));
+    HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    if (v == 0 || ms < best) {
+      best = ms;
+      bi = v;
+    }
+  }
+  HIP_CHECK(hipMemcpyAsync(buf, save.p, bytes, hipMemcpyDeviceToDevice, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  tree->tune[key] = bi;
+  F.tuned += 1;
+  return bi;
+}
+
+// Fronts sorted by pivot count, descending (bucketed launches).
+static std::vector<FrontDev> sorted_by_p(const std::vector<FrontDev>& fh) {
+  std::vector<FrontDev> out(fh);
+  std::stable_sort(out.begin(), out.end(),
+                   [](const FrontDev& x, const FrontDev& y) { return x.p > y.p; });
+  return out;
+}
+
 template <typename T, typename TS>
 static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
@@ -635,8 +734,16 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
                        static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps, S.trips,
                        F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt);
   HIP_CHECK(hipGetLastError());
-  batched_ldl<T>(static_cast<T*>(D.pool), S.fh, S.fronts, D.info, st);
-  apply_form<T>(F.mem, static_cast<T*>(D.pool), S.fh, S.fronts, st);
+  // elimination and apply form in buckets of pivot count (sorted fronts)
+  const std::vector<FrontDev> fs = sorted_by_p(S.fh);
+  const FrontDev* fs_d = F.mem.upload(fs, st);
+  const int var = tune_choice(
+      F, tune_key(FAM_LDL, int(sizeof(T)), S.pmax, S.smax, S.ncell), LDL_VARIANTS, LDL_MFMA, D.pool,
+      size_t(S.elems) * sizeof(T), st, [&](int v) {
+        batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, v);
+      });
+  batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, var);
+  apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, st, false, true);
   pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
                  &D.dinv, st);
 }
@@ -773,11 +880,43 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   if (smem > 64 * 1024)
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
+  if (smem > 64 * 1024)
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr_queue<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
   const double tau = sizeof(T) == 8 ? 1e-10 : 1e-5;
-  hipLaunchKernelGGL(k_cpqr<T>, dim3(G.ngroup), dim3(kThreads), smem, st, static_cast<T*>(G.gw),
-                     static_cast<T*>(G.tpool), G.groups, F.eps, tau, G.kout, G.perm,
-                     G.perm_stride);
-  HIP_CHECK(hipGetLastError());
+  {
+    // queue order: largest work (|c^N| |c|^2) first
+    std::vector<int32_t> order(G.ngroup);
+    for (int g = 0; g < G.ngroup; ++g) order[g] = g;
+    int nnmax = 0;
+    for (const GroupDev& d : G.gh) nnmax = std::max(nnmax, int(d.nn));
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      const GroupDev &a = G.gh[x], &b = G.gh[y];
+      return double(a.nn + a.nc) * a.nc * a.nc > double(b.nn + b.nc) * b.nc * b.nc;
+    });
+    const int32_t* order_d = F.mem.upload(order, st);
+    int* counter = F.mem.get<int>(1);
+    int dev = 0, ncu = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned qgrid = unsigned(std::min(G.ngroup, std::max(1, ncu) * 4));
+    auto run = [&](int v) {
+      if (v == 1) {
+        HIP_CHECK(hipMemsetAsync(counter, 0, sizeof(int), st));
+        hipLaunchKernelGGL(k_cpqr_queue<T>, dim3(qgrid), dim3(kThreads), smem, st,
+                           static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, F.eps, tau,
+                           G.kout, G.perm, G.perm_stride, order_d, G.ngroup, counter);
+      } else {
+        hipLaunchKernelGGL(k_cpqr<T>, dim3(G.ngroup), dim3(kThreads), smem, st,
+                           static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, F.eps, tau,
+                           G.kout, G.perm, G.perm_stride);
+      }
+      HIP_CHECK(hipGetLastError());
+    };
+    const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 2,
+                                1, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
+    run(var);
+  }
 
   // Pre-launch: the skeleton fronts of every group are formed, eliminated,
   // turned into the apply form and packed before the ranks reach the host.
@@ -915,8 +1054,22 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                      static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
                      G.perm, G.perm_stride, G.gsel, static_cast<const int32_t*>(nullptr));
   HIP_CHECK(hipGetLastError());
-  batched_ldl<T>(static_cast<T*>(G.fg), G.ff, G.fgfronts, G.info, st);
-  apply_form<T>(F.mem, static_cast<T*>(G.fg), G.ff, G.fgfronts, st);
+  {
+    const std::vector<FrontDev> fs = sorted_by_p(G.ff);
+    const FrontDev* fs_d = F.mem.upload(fs, st);
+    int pmx = 0, smx = 0;
+    for (const FrontDev& f : fs) {
+      pmx = std::max(pmx, f.p);
+      smx = std::max(smx, f.s);
+    }
+    const int var = tune_choice(
+        F, tune_key(FAM_LDL, int(sizeof(T)), pmx, smx, G.nskel), LDL_VARIANTS, LDL_MFMA, G.fg,
+        size_t(fg_off) * sizeof(T), st, [&](int v) {
+          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, v);
+        });
+    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, var);
+    apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true);
+  }
   F.skel_panels += (rmax + kNB - 1) / kNB;
   build_sweep(G.sw, G.ff, false);
   upload_sweep(G.sw, F.mem, st);
@@ -1014,6 +1167,7 @@ static void fill_stats(hifde_factor_s& F) {
   s.rank_mae = F.rank_groups > 0 ? F.rank_abs_err / double(F.rank_groups) : 0.0;
   s.rebuckets = F.rebuckets;
   s.skel_panels = F.skel_panels;
+  s.tuned = F.tuned;
 }
 
 // ---------------------------------------------------------------------------
@@ -1478,8 +1632,8 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
   if (!tree || !a) return fail(HIFDE_EINVAL, "tree or a is NULL");
   if (!(eps >= 0.0 && eps < 1.0)) return fail(HIFDE_EINVAL, "eps must lie in [0, 1)");
   if (prec != HIFDE_FP64 && prec != HIFDE_MIXED) return fail(HIFDE_EINVAL, "unknown precision");
-  if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_NO_GRAPH |
-                        HIFDE_PRESIZE_WORST_CASE))
+  if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_AUTOTUNE |
+                        HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "unknown flags");
   if ((flags & HIFDE_USE_RANK_MODEL) && (flags & HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "HIFDE_USE_RANK_MODEL and HIFDE_PRESIZE_WORST_CASE exclude each other");
@@ -1494,6 +1648,8 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     const int presize = (flags & HIFDE_USE_RANK_MODEL) ? 1 : (flags & HIFDE_PRESIZE_WORST_CASE) ? 2 : 0;
     F->presize = presize;
     F->model = presize == 1 ? tree->model_d.as<float>() : nullptr;
+    F->autotune = (flags & HIFDE_AUTOTUNE) != 0;
+    F->tree = tree;
     build_factor(*F, tree, a, b, eps, prec, st);
     F->use_graph = !(flags & HIFDE_NO_GRAPH);
     fill_stats(*F);
@@ -1503,6 +1659,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
       hifde_factor_s F2;
       F2.presize = presize;
       F2.model = F->model;
+      F2.tree = tree;
       build_factor(F2, tree, a, b, eps, prec, st);
       compare_factors(*F, F2, st);
     }

@@ -1,0 +1,56 @@
+"""GPU: the bucketed, persistent and autotuned launch paths.
+
+Every launch variant the autotuner can pick (trailing update of the batched
+LDL^T on FMA or on the matrix cores; ID launch as one work-group per group
+or as a persistent queue, largest first) must give the oracle's index sets
+and, in FP64, F^-1 f within the parity bar; autotuning records its choices
+in the tree and later factorizations reuse them bit for bit.
+"""
+import numpy as np
+import pytest
+
+from synth import workloads as W
+
+from _helpers import compare_sets, oracle_factor, rel_residual, torch_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+@pytest.mark.parametrize("force", ["ldl=0,cpqr=0", "ldl=1,cpqr=1", "ldl=0,cpqr=1"])
+@pytest.mark.parametrize("case", [(2, 64, 8, 1e-6, "bernoulli_contrast", 2),
+                                  (3, 16, 2, 1e-3, "lognormal_grf", 4)])
+def test_every_variant_matches_oracle(force, case, monkeypatch):
+    import paper_1307_2895_amd as H
+    from oracle import hifde as OH
+    monkeypatch.setenv("HIFDE_TUNE_FORCE", force)   # read by each hifde_factor call
+    print(f"case {case} {force}", flush=True)
+    dim, n, m, eps, field, seed = case
+    a = W.make_field(dim, n, field, seed)
+    OF = oracle_factor(dim, n, m, a, eps)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    F = H.hifde_factor(T, torch_inputs(a), None, eps, 0)
+    cm, gm, sm, first = compare_sets(OF, F)
+    assert cm == 0 and gm == 0 and sm == 0, (cm, gm, sm)
+    f = W.make_rhs(n ** dim, 2, 3)
+    u = H.hifde_solve(F, torch.from_numpy(f).cuda()).cpu().numpy()
+    ur = OH.solve(OF, f)
+    assert np.max(np.abs(u - ur)) <= 1e-8 * np.max(np.abs(ur))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_caches_choices_in_tree(prec):
+    import paper_1307_2895_amd as H
+    dim, n, m = 2, 128, 8
+    a = W.make_field(dim, n, "loguniform", 6)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    F1 = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec, flags=H.HIFDE_AUTOTUNE)
+    s1 = H.hifde_stats(F1)
+    assert s1["tuned"] > 0
+    F2 = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+    assert H.hifde_stats(F2)["tuned"] == 0
+    F3 = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec, flags=H.HIFDE_AUTOTUNE)
+    assert H.hifde_stats(F3)["tuned"] == 0          # every bucket already chosen
+    f = torch.from_numpy(W.make_rhs(n * n, 3, 2)).cuda()
+    u1, u2 = H.hifde_solve(F1, f), H.hifde_solve(F2, f)
+    assert torch.equal(u1, u2)
