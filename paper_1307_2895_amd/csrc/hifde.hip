@@ -533,7 +533,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
   for (int j0 = 0; j0 < pmax; j0 += kNB) {
     const unsigned nf = active_fronts(fh, j0, sorted);
     if (nf == 0) break;
-    int64_t maxt = 0;
+    int64_t maxt = 0, maxr = 0;
     for (const auto& f : fh) {
       if (j0 >= f.p) continue;
       int r0 = bounds ? j0 + 1 : std::min(j0 + kNB, f.p);
@@ -541,8 +541,14 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
       if (nt <= 0) continue;
       int64_t T_ = (nt + kTB - 1) / kTB;
       maxt = std::max(maxt, T_ * (T_ + 1) / 2);
+      maxr = std::max(maxr, (nt + 63) / 64);
     }
-    hipLaunchKernelGGL(k_ldl_panel<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, j0, info_d);
+    hipLaunchKernelGGL(k_ldl_diag<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, j0, info_d);
+    if (maxr > 0) {
+      if (maxr > 65535) throw Error(HIFDE_EINVAL, "front too large for the panel grid");
+      hipLaunchKernelGGL(k_ldl_rows<T>, dim3(nf, unsigned(maxr)), dim3(kThreads), 0, st, pool,
+                         fronts_d, j0);
+    }
     if (maxt > 0) {
       if (maxt > 65535) throw Error(HIFDE_EINVAL, "front too large for the trailing-update grid");
       if (variant == LDL_MFMA)
@@ -559,7 +565,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
 template <typename T>
 static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
                        const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
-                       bool sorted = false) {
+                       bool sorted = false, int variant = 1) {
   if (fh.empty()) return;
   std::vector<int64_t> toff(fh.size());
   int64_t tot = 0;
@@ -582,8 +588,12 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
     if (na == 0) continue;
     if (tiles > 0) {
       if (tiles > 65535) throw Error(HIFDE_EINVAL, "front too large for the inversion grid");
-      hipLaunchKernelGGL(k_inv_step<T>, dim3(na, unsigned(tiles)), dim3(kThreads), 0, st, pool,
-                         fronts_d, J, tmp, toff_d);
+      if (variant == 1)
+        hipLaunchKernelGGL(k_inv_step_mfma<T>, dim3(na, unsigned(tiles)), dim3(kThreads), 0, st,
+                           pool, fronts_d, J, tmp, toff_d);
+      else
+        hipLaunchKernelGGL(k_inv_step<T>, dim3(na, unsigned(tiles)), dim3(kThreads), 0, st, pool,
+                           fronts_d, J, tmp, toff_d);
     }
     hipLaunchKernelGGL(k_inv_commit<T>, dim3(na), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
                        toff_d);
@@ -634,7 +644,7 @@ static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
 // an unseen bucket runs every variant once on a snapshot of the data it
 // modifies (buf, bytes), timed with events, keeps the fastest for the tree,
 // and restores the data for the real run.
-enum { FAM_LDL = 1, FAM_CPQR = 2 };
+enum { FAM_LDL = 1, FAM_CPQR = 2, FAM_INV = 3 };
 static uint64_t tune_key(int fam, int esz, int a, int b, int c) {
   auto bucket = [](int v) {
     int k = 0;
@@ -649,7 +659,8 @@ static uint64_t tune_key(int fam, int esz, int a, int b, int c) {
 static int forced_variant(int fam) {
   const char* e = getenv("HIFDE_TUNE_FORCE");
   if (!e) return -1;
-  const std::string s(e), name = fam == FAM_LDL ? "ldl=" : "cpqr=";
+  const std::string s(e);
+  const std::string name = fam == FAM_LDL ? "ldl=" : fam == FAM_CPQR ? "cpqr=" : "inv=";
   const size_t at = s.find(name);
   if (at == std::string::npos) return -1;
   return std::atoi(s.c_str() + at + name.size());
@@ -743,7 +754,11 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
         batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, v);
       });
   batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, var);
-  apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, st, false, true);
+  const int ivar = tune_choice(
+      F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 2, 1, D.pool,
+      size_t(S.elems) * sizeof(T), st,
+      [&](int v) { apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, st, false, true, v); });
+  apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, st, false, true, ivar);
   pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
                  &D.dinv, st);
 }
@@ -914,7 +929,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       HIP_CHECK(hipGetLastError());
     };
     const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 2,
-                                1, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
+                                0, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
     run(var);
   }
 
@@ -1068,7 +1083,11 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
           batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, v);
         });
     batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, var);
-    apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true);
+    const int ivar = tune_choice(
+        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 2, 1, G.fg,
+        size_t(fg_off) * sizeof(T), st,
+        [&](int v) { apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, v); });
+    apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, ivar);
   }
   F.skel_panels += (rmax + kNB - 1) / kNB;
   build_sweep(G.sw, G.ff, false);
