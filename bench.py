@@ -30,9 +30,10 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 # The kernel the roofline object describes: the upward sweep of F^-1 over
-# cells and skeleton fronts (every launch of k_sweep_up<float, float, 1>:
-# all levels, both cell colors and the groups).
-DOMINANT_KERNEL = "k_sweep_up<float, float, 1>"
+# cells and skeleton fronts (every launch of k_sweep_up<float, float, 1,
+# true>, the 16-right-hand-side instance: all levels, both cell colors and
+# the groups).
+DOMINANT_KERNEL = "k_sweep_up<float, float, 1, true>"
 DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
 CALIB_COPY_BYTES = 512 << 20
 
