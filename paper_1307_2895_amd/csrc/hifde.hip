@@ -645,6 +645,8 @@ static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
 // modifies (buf, bytes), timed with events, keeps the fastest for the tree,
 // and restores the data for the real run.
 enum { FAM_LDL = 1, FAM_CPQR = 2, FAM_INV = 3 };
+constexpr int kCpqrWideFrom = 128;   // |c| from which the ID defaults to the wide form
+constexpr int kAsmWideFrom = 512;    // front size from which extend-add goes wide
 static uint64_t tune_key(int fam, int esz, int a, int b, int c) {
   auto bucket = [](int v) {
     int k = 0;
@@ -740,10 +742,30 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   D.info = F.mem.get<int>(std::max(1, S.ncell));
   HIP_CHECK(hipMemsetAsync(D.info, 0, sizeof(int) * std::max(1, S.ncell), st));
   PoolTable pt = pools_for_level(F, l - 1);
-  if (S.ncell > 0)
-    hipLaunchKernelGGL((k_assemble<T, TS>), dim3(S.ncell), dim3(kThreads), 0, st,
-                       static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps, S.trips,
-                       F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt);
+  if (S.ncell > 0) {
+    if (S.smax >= kAsmWideFrom) {
+      // large fronts: one launch per source round, columns over work-groups
+      int rounds = 0, dmax = 0;
+      int64_t tmax = 0;
+      for (const FrontDev& f : S.fh) {
+        rounds = std::max(rounds, f.src_end - f.src_begin);
+        tmax = std::max<int64_t>(tmax, f.trip_end - f.trip_begin);
+      }
+      for (const SrcDev& d : S.srcs_h) dmax = std::max(dmax, d.dim);
+      for (int r = 0; r < rounds; ++r)
+        hipLaunchKernelGGL((k_assemble_round<T, TS>), dim3(S.ncell, (dmax + kAsmCols - 1) / kAsmCols),
+                           dim3(kThreads), 0, st, static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps,
+                           r, pt);
+      if (tmax > 0)
+        hipLaunchKernelGGL(k_assemble_trips<T>, dim3(S.ncell, unsigned((tmax + 4095) / 4096)),
+                           dim3(kThreads), 0, st, static_cast<T*>(D.pool), S.fronts, S.trips,
+                           F.diag.as<double>(), F.offd.as<double>(), F.g.N);
+    } else {
+      hipLaunchKernelGGL((k_assemble<T, TS>), dim3(S.ncell), dim3(kThreads), 0, st,
+                         static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps, S.trips,
+                         F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt);
+    }
+  }
   HIP_CHECK(hipGetLastError());
   // elimination and apply form in buckets of pivot count (sorted fronts)
   const std::vector<FrontDev> fs = sorted_by_p(S.fh);
@@ -832,6 +854,27 @@ static void predict_ranks(hifde_factor_s& F, GroupLevel& G, int l) {
   HIP_CHECK(hipGetLastError());
 }
 
+// Skeleton fronts: one work-group per group, or for large groups two
+// launches (B_sr and E columns, then B_rr columns) over column chunks.
+template <typename T>
+static void launch_group_front(GroupLevel& G, int nblocks, int ncmax, const int32_t* gsel,
+                               const int32_t* kdev, hipStream_t st) {
+  if (ncmax < kCpqrWideFrom) {
+    hipLaunchKernelGGL(k_group_front<T>, dim3(nblocks), dim3(kThreads), 0, st,
+                       static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
+                       static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
+                       G.perm, G.perm_stride, gsel, kdev, -1);
+  } else {
+    const unsigned ch = unsigned((ncmax + kAsmCols - 1) / kAsmCols);
+    for (int phase = 0; phase < 2; ++phase)
+      hipLaunchKernelGGL(k_group_front<T>, dim3(nblocks, ch), dim3(kThreads), 0, st,
+                         static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
+                         static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
+                         G.perm, G.perm_stride, gsel, kdev, phase);
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
@@ -883,11 +926,34 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     }
   G.groups = F.mem.upload(G.gh, st);
   PoolTable pt_cur{{F.cl[l].pool, nullptr, nullptr}};
-  hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
-                     static_cast<T*>(G.gw), static_cast<const T*>(G.base), G.groups, S.gsrcs,
-                     S.maps, S.gtrips, F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_cur);
-  HIP_CHECK(hipGetLastError());
   const int ncmax = S.ncmax;
+  if (ncmax >= kCpqrWideFrom) {
+    // large groups: source rounds, base block, loose links over column chunks
+    int rounds = 0, dmax = 0;
+    int64_t tmax = 0;
+    for (const GroupDev& d : G.gh) {
+      rounds = std::max(rounds, d.src_end - d.src_begin);
+      tmax = std::max<int64_t>(tmax, d.trip_end - d.trip_begin);
+    }
+    for (const SrcDev& d : S.gsrcs_h) dmax = std::max(dmax, d.dim);
+    const unsigned ng = unsigned(G.ngroup);
+    for (int r = 0; r < rounds; ++r)
+      hipLaunchKernelGGL(k_gather_round<T>, dim3(ng, (dmax + kAsmCols - 1) / kAsmCols),
+                         dim3(kThreads), 0, st, static_cast<T*>(G.gw), G.groups, S.gsrcs, S.maps, r,
+                         pt_cur);
+    hipLaunchKernelGGL(k_gather_base<T>, dim3(ng, (ncmax + kAsmCols - 1) / kAsmCols),
+                       dim3(kThreads), 0, st, static_cast<T*>(G.gw),
+                       static_cast<const T*>(G.base), G.groups);
+    if (tmax > 0)
+      hipLaunchKernelGGL(k_gather_trips<T>, dim3(ng, unsigned((tmax + 4095) / 4096)),
+                         dim3(kThreads), 0, st, static_cast<T*>(G.gw), G.groups, S.gtrips,
+                         F.diag.as<double>(), F.offd.as<double>(), F.g.N);
+  } else {
+    hipLaunchKernelGGL(k_group_gather<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
+                       static_cast<T*>(G.gw), static_cast<const T*>(G.base), G.groups, S.gsrcs,
+                       S.maps, S.gtrips, F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_cur);
+  }
+  HIP_CHECK(hipGetLastError());
   G.perm_stride = ncmax;
   G.kout = F.mem.get<int32_t>(G.ngroup);
   G.perm = F.mem.get<int32_t>(size_t(G.ngroup) * ncmax);
@@ -915,7 +981,56 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     HIP_CHECK(hipGetDevice(&dev));
     HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const unsigned qgrid = unsigned(std::min(G.ngroup, std::max(1, ncu) * 4));
+    // wide form: every group of the launch, all steps in lock-step
+    int maxsteps = 0;
+    std::vector<int64_t> noff(G.ngroup);
+    int64_t ntot = 0;
+    for (int g = 0; g < G.ngroup; ++g) {
+      noff[g] = ntot;
+      ntot += G.gh[g].nc;
+      maxsteps = std::max(maxsteps, std::min<int>(G.gh[g].nn, G.gh[g].nc));
+    }
+    auto run_wide = [&] {
+      std::vector<int32_t> list(G.ngroup);
+      for (int g = 0; g < G.ngroup; ++g) list[g] = g;
+      const int32_t* list_d = F.mem.upload(list, st);
+      const int64_t* noff_d = F.mem.upload(noff, st);
+      T* norms = F.mem.get<T>(size_t(std::max<int64_t>(ntot, 1)));
+      int32_t* permw = F.mem.get<int32_t>(size_t(std::max<int64_t>(ntot, 1)));
+      CpqrWide<T>* stw = F.mem.get<CpqrWide<T>>(G.ngroup);
+      int* live_d = F.mem.get<int>(1);
+      const unsigned ng = unsigned(G.ngroup);
+      const unsigned chunks = unsigned((ncmax + kCpqrChunk - 1) / kCpqrChunk);
+      hipLaunchKernelGGL(k_cpqr_w_init<T>, dim3(ng, chunks), dim3(kThreads), 0, st,
+                         static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, permw, stw);
+      for (int j = 0; j < maxsteps; ++j) {
+        hipLaunchKernelGGL(k_cpqr_w_pivot<T>, dim3(ng), dim3(kThreads), 0, st,
+                           static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, permw, stw, j,
+                           F.eps, tau);
+        const unsigned uch = unsigned(std::max(1, (ncmax - j - 1 + kCpqrChunk - 1) / kCpqrChunk));
+        hipLaunchKernelGGL(k_cpqr_w_update<T>, dim3(ng, uch), dim3(kThreads), 0, st,
+                           static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, stw, j);
+        if ((j & 31) == 31) {   // stop once every group has its rank
+          int live = 0;
+          hipLaunchKernelGGL(k_cpqr_w_live<T>, dim3(1), dim3(kThreads), 0, st, stw, G.ngroup,
+                             live_d);
+          HIP_CHECK(hipMemcpyAsync(&live, live_d, sizeof(int), hipMemcpyDeviceToHost, st));
+          HIP_CHECK(hipStreamSynchronize(st));
+          if (live == 0) break;
+        }
+      }
+      hipLaunchKernelGGL(k_cpqr_w_tsolve<T>, dim3(ng, unsigned((ncmax + 63) / 64)), dim3(kThreads),
+                         0, st, static_cast<T*>(G.gw), G.groups, list_d, stw);
+      hipLaunchKernelGGL(k_cpqr_w_finish<T>, dim3(ng), dim3(kThreads), size_t(ncmax) * sizeof(int),
+                         st, static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, list_d,
+                         noff_d, permw, stw, G.kout, G.perm, G.perm_stride);
+      HIP_CHECK(hipGetLastError());
+    };
     auto run = [&](int v) {
+      if (v == 2) {
+        run_wide();
+        return;
+      }
       if (v == 1) {
         HIP_CHECK(hipMemsetAsync(counter, 0, sizeof(int), st));
         hipLaunchKernelGGL(k_cpqr_queue<T>, dim3(qgrid), dim3(kThreads), smem, st,
@@ -928,8 +1043,10 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       }
       HIP_CHECK(hipGetLastError());
     };
-    const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 2,
-                                0, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
+    // default: the wide form once groups are too large for one work-group
+    const int dflt = ncmax >= kCpqrWideFrom ? 2 : 0;
+    const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 3,
+                                dflt, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
     run(var);
   }
 
@@ -949,11 +1066,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                        G.fgfronts, sall.packs);
     HIP_CHECK(hipMemsetAsync(G.fg, 0, size_t(fg_all) * sizeof(T), st));
     HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ngroup, st));
-    hipLaunchKernelGGL(k_group_front<T>, dim3(G.ngroup), dim3(kThreads), 0, st,
-                       static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
-                       static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
-                       G.perm, G.perm_stride, static_cast<const int32_t*>(nullptr), G.kout);
-    HIP_CHECK(hipGetLastError());
+    launch_group_front<T>(G, G.ngroup, ncmax, static_cast<const int32_t*>(nullptr), G.kout, st);
     batched_ldl<T>(static_cast<T*>(G.fg), fall, G.fgfronts, G.info, st, true);
     apply_form<T>(F.mem, static_cast<T*>(G.fg), fall, G.fgfronts, st, true);
     F.skel_panels += (bound + kNB - 1) / kNB;
@@ -1064,11 +1177,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.fgfronts = F.mem.upload(G.ff, st);
   G.info = F.mem.get<int>(G.ff.size());
   HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ff.size(), st));
-  hipLaunchKernelGGL(k_group_front<T>, dim3(G.nskel), dim3(kThreads), 0, st,
-                     static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
-                     static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
-                     G.perm, G.perm_stride, G.gsel, static_cast<const int32_t*>(nullptr));
-  HIP_CHECK(hipGetLastError());
+  launch_group_front<T>(G, G.nskel, G.ncskel, G.gsel, static_cast<const int32_t*>(nullptr), st);
   {
     const std::vector<FrontDev> fs = sorted_by_p(G.ff);
     const FrontDev* fs_d = F.mem.upload(fs, st);
@@ -1280,6 +1389,18 @@ static SweepShape sweep_shape(int nitems, int nrhs, int krows) {
   return g;
 }
 
+// Output chunks of the largest group's interpolation step.
+static unsigned interp_chunks(const GroupLevel& G, int nrhs, bool up) {
+  int64_t m = 1;
+  for (int gi : G.gsel_h) {
+    const GroupDev& d = G.gh[gi];
+    m = std::max<int64_t>(m, int64_t(up ? d.nc - d.k : d.k) * nrhs);
+  }
+  const int64_t ch = (m + kInterpChunk - 1) / kInterpChunk;
+  if (ch > 65535) throw Error(HIFDE_EINVAL, "interpolation step too large for its grid");
+  return unsigned(ch);
+}
+
 template <typename T, typename TX>
 static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, int c,
                      const void* pk, const void* dinv, const int32_t* idx, TX* X, TX* Z, int nrhs,
@@ -1343,8 +1464,9 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
     if (G.nskel > 0) {
       const Work w = F.prof_mask ? interp_work(G, true, nrhs, esz, xsz) : Work{0, 0};
       timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_interp_up<T, TX>), dim3(G.nskel), dim3(kThreads), 0, st, G.groups,
-                           G.gsel, static_cast<const T*>(G.tpool), G.idx, X, nrhs);
+        hipLaunchKernelGGL((k_interp_up<T, TX>), dim3(G.nskel, interp_chunks(G, nrhs, true)),
+                           dim3(kThreads), 0, st, G.groups, G.gsel,
+                           static_cast<const T*>(G.tpool), G.idx, X, nrhs);
       });
       sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, G.sw, 0, G.pk, G.dinv, G.idx, X, Z, nrhs, st);
     }
@@ -1359,8 +1481,9 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
       sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pt, G.idx, X, Z, nrhs, st);
       const Work w = F.prof_mask ? interp_work(G, false, nrhs, esz, xsz) : Work{0, 0};
       timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_interp_down<T, TX>), dim3(G.nskel), dim3(kThreads), 0, st, G.groups,
-                           G.gsel, static_cast<const T*>(G.tpool), G.idx, X, nrhs);
+        hipLaunchKernelGGL((k_interp_down<T, TX>), dim3(G.nskel, interp_chunks(G, nrhs, false)),
+                           dim3(kThreads), 0, st, G.groups, G.gsel,
+                           static_cast<const T*>(G.tpool), G.idx, X, nrhs);
       });
     }
     CellLevel& C = F.cl[l];

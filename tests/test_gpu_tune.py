@@ -2,7 +2,8 @@
 
 Every launch variant the autotuner can pick (trailing update of the batched
 LDL^T and the apply-form step on FMA or on the matrix cores; ID launch as
-one work-group per group or as a persistent queue, largest first) must give the oracle's index sets
+one work-group per group, as a persistent queue, largest first, or in the
+wide form that spreads each step over many work-groups) must give the oracle's index sets
 and, in FP64, F^-1 f within the parity bar; autotuning records its choices
 in the tree and later factorizations reuse them bit for bit.
 """
@@ -18,7 +19,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 @pytest.mark.parametrize("force", ["ldl=0,cpqr=0,inv=0", "ldl=1,cpqr=1,inv=1",
-                                   "ldl=0,cpqr=1,inv=1", "ldl=1,cpqr=0,inv=0"])
+                                   "ldl=0,cpqr=1,inv=1", "ldl=1,cpqr=0,inv=0",
+                                   "ldl=1,cpqr=2,inv=1"])
 @pytest.mark.parametrize("case", [(2, 64, 8, 1e-6, "bernoulli_contrast", 2),
                                   (3, 16, 2, 1e-3, "lognormal_grf", 4)])
 def test_every_variant_matches_oracle(force, case, monkeypatch):
