@@ -697,6 +697,9 @@ static int tune_choice(hifde_factor_s& F, uint64_t key, int nvar, int dflt, void
     HIP_CHECK(hipEventSynchronize(b));
     float ms = 0.f;
     HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    if (getenv("HIFDE_TIMING"))
+      fprintf(stderr, "[hifde] tune family %d key %016llx variant %d: %.3f ms\n", int(key >> 56),
+              static_cast<unsigned long long>(key), v, ms);
     if (v == 0 || ms < best) {
       best = ms;
       bi = v;
@@ -961,9 +964,12 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   if (smem > 64 * 1024)
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
-  if (smem > 64 * 1024)
+  if (smem > 64 * 1024) {
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr_queue<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr_1k<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
+  }
   const double tau = sizeof(T) == 8 ? 1e-10 : 1e-5;
   {
     // queue order: largest work (|c^N| |c|^2) first
@@ -1031,6 +1037,13 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
         run_wide();
         return;
       }
+      if (v == 3) {
+        hipLaunchKernelGGL(k_cpqr_1k<T>, dim3(G.ngroup), dim3(1024), smem, st,
+                           static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, F.eps, tau,
+                           G.kout, G.perm, G.perm_stride);
+        HIP_CHECK(hipGetLastError());
+        return;
+      }
       if (v == 1) {
         HIP_CHECK(hipMemsetAsync(counter, 0, sizeof(int), st));
         hipLaunchKernelGGL(k_cpqr_queue<T>, dim3(qgrid), dim3(kThreads), smem, st,
@@ -1044,8 +1057,8 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       HIP_CHECK(hipGetLastError());
     };
     // default: the wide form once groups are too large for one work-group
-    const int dflt = ncmax >= kCpqrWideFrom ? 2 : 0;
-    const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 3,
+    const int dflt = ncmax >= kCpqrWideFrom ? 2 : G.ngroup < 256 ? 3 : 0;
+    const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 4,
                                 dflt, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
     run(var);
   }

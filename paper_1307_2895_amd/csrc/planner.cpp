@@ -3,43 +3,123 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdlib>
 #include <exception>
+#include <functional>
+#include <mutex>
 #include <stdexcept>
 #include <thread>
 
 namespace hifde {
 
-// Runs f(i, worker) for i in [0, n) on up to `workers` threads, `grain`
-// consecutive items at a time; the first exception is rethrown here.
+// A process-wide pool of planning threads: started once, parked on a
+// condition variable between jobs.  A job is a function of (item, worker)
+// over [0, n), taken `grain` items at a time from an atomic counter; the
+// calling thread works as worker 0.  One job runs at a time.
+namespace {
+class PlanPool {
+ public:
+  static PlanPool& get() {
+    static PlanPool pool;
+    return pool;
+  }
+  int size() const { return int(threads_.size()) + 1; }
+
+  void run(size_t n, size_t grain, int workers, const std::function<void(size_t, int)>& f) {
+    std::lock_guard<std::mutex> one(job_mutex_);
+    const int helpers = std::min<int>(workers, size()) - 1;
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      fn_ = &f;
+      n_ = n;
+      grain_ = grain;
+      next_.store(0);
+      failed_.store(false);
+      err_ = nullptr;
+      helpers_ = helpers;
+      pending_ = helpers;
+      ++epoch_;
+    }
+    cv_.notify_all();
+    work(0);
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [&] { return pending_ == 0; });
+    fn_ = nullptr;
+    if (err_) std::rethrow_exception(err_);
+  }
+
+ private:
+  PlanPool() {
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int n = int(std::min(16u, hw));
+    if (const char* e = std::getenv("HIFDE_PLAN_THREADS")) n = std::max(1, std::atoi(e));
+    for (int w = 1; w < n; ++w) threads_.emplace_back([this, w] { loop(w); });
+  }
+  ~PlanPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  void work(int w) {
+    try {
+      for (;;) {
+        const size_t b = next_.fetch_add(grain_);
+        if (b >= n_ || failed_.load()) break;
+        const size_t e = std::min(n_, b + grain_);
+        for (size_t i = b; i < e; ++i) (*fn_)(i, w);
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(m_);
+      if (!failed_.exchange(true)) err_ = std::current_exception();
+    }
+  }
+  void loop(int w) {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return stop_ || epoch_ != seen; });
+        if (stop_) return;
+        seen = epoch_;
+        if (w > helpers_) continue;   // not needed for this job
+      }
+      work(w);
+      std::lock_guard<std::mutex> lk(m_);
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+
+  std::vector<std::thread> threads_;
+  std::mutex m_, job_mutex_;
+  std::condition_variable cv_, done_;
+  const std::function<void(size_t, int)>* fn_ = nullptr;
+  size_t n_ = 0, grain_ = 1;
+  std::atomic<size_t> next_{0};
+  std::atomic<bool> failed_{false};
+  std::exception_ptr err_;
+  int helpers_ = 0, pending_ = 0;
+  uint64_t epoch_ = 0;
+  bool stop_ = false;
+};
+}  // namespace
+
+// Runs f(i, worker) for i in [0, n) on up to `workers` threads (worker ids
+// below `workers`), `grain` items at a time; the first exception is
+// rethrown here.
 template <class F>
 static void parallel_for(size_t n, size_t grain, int workers, F&& f) {
-  size_t chunks = (n + grain - 1) / grain;
-  int nt = int(std::min<size_t>(size_t(workers), chunks));
+  const size_t chunks = (n + grain - 1) / grain;
+  const int nt = int(std::min<size_t>(size_t(workers), chunks));
   if (nt <= 1) {
     for (size_t i = 0; i < n; ++i) f(i, 0);
     return;
   }
-  std::atomic<size_t> next{0};
-  std::exception_ptr err;
-  std::atomic<bool> failed{false};
-  auto body = [&](int w) {
-    try {
-      for (;;) {
-        const size_t b = next.fetch_add(grain);
-        if (b >= n || failed.load()) break;
-        const size_t e = std::min(n, b + grain);
-        for (size_t i = b; i < e; ++i) f(i, w);
-      }
-    } catch (...) {
-      if (!failed.exchange(true)) err = std::current_exception();
-    }
-  };
-  std::vector<std::thread> th;
-  for (int w = 1; w < nt; ++w) th.emplace_back(body, w);
-  body(0);
-  for (auto& t : th) t.join();
-  if (err) std::rethrow_exception(err);
+  const std::function<void(size_t, int)> fn = [&](size_t i, int w) { f(i, w); };
+  PlanPool::get().run(n, grain, nt, fn);
 }
 
 std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
@@ -71,8 +151,7 @@ std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
 Planner::Planner(const Geom& g) : g_(g) {
   active_.assign(g_.N, 1);
   grouped_.assign(g_.N, 0);
-  workers_ = int(std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())));
-  if (const char* e = std::getenv("HIFDE_PLAN_THREADS")) workers_ = std::max(1, std::atoi(e));
+  workers_ = PlanPool::get().size();
   loc_.resize(workers_);
   own0_.assign(g_.N, -1);
   own1_.assign(g_.N, -1);
