@@ -121,7 +121,10 @@ typedef struct {
 /* Build the uniform tree of Sections 3.1-3.2 and 4.1-4.2: n unknowns per side,
  * leaf boxes of `leaf` unknowns per side, L = log2(n/leaf) levels.  The first
  * `skip_levels` fractional levels are not skeletonized (Section 5).
- * Host-only; no device work.
+ * Host-only; no device work.  The tree also keeps, for reuse by its later
+ * factorizations, the device memory of factorizations that were freed; it
+ * is released when the tree and all its factorizations are freed (or, when
+ * a device allocation fails, before it is retried).
  * EINVAL: dim not 2 or 3, leaf < 2, n/leaf not a power of two >= 2,
  * skip_levels < 0, N >= 2^31. */
 int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels,
@@ -166,7 +169,8 @@ int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
                  double* y, int64_t ldy, void* hip_stream);
 
 /* Kernel timing.  Launches of the selected kernel classes are bracketed by
- * HIP events on the stream they run on; hifde_profile_read reports, per
+ * HIP events on the stream they run on (while profiling, F^-1 runs as direct
+ * launches, not as the captured graph); hifde_profile_read reports, per
  * class, the launches timed, their summed event time and their algorithmic
  * traffic and flops (the bytes of the stored factor blocks, index lists and
  * vector rows the launch must touch, and the multiply-adds the sweep
@@ -264,6 +268,8 @@ int hifde_export_sets(hifde_factor_t F, int level2, hifde_sets_t* out);
 int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level,
                       hifde_factor_t* out);
 
+/* Free a tree (its factorizations stay valid) or a factor (waits for the
+ * device to finish before its memory returns to the tree's pool). */
 void hifde_tree_free(hifde_tree_t tree);
 void hifde_factor_free(hifde_factor_t F);
 const char* hifde_last_error(void);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -39,40 +40,98 @@ struct Error : std::runtime_error {
   } while (0)
 
 // Owning device allocation.
+struct MemPool;
+
+// A device allocation; with a pool, taken from and given back to it.
 struct DevMem {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0, cap = 0;         // requested size, size of the block
+  MemPool* pool = nullptr;
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap), pool(o.pool) {
     o.p = nullptr;
-    o.bytes = 0;
+    o.bytes = o.cap = 0;
   }
   DevMem& operator=(DevMem&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       bytes = o.bytes;
+      cap = o.cap;
+      pool = o.pool;
       o.p = nullptr;
-      o.bytes = 0;
+      o.bytes = o.cap = 0;
     }
     return *this;
   }
   ~DevMem() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  void alloc(size_t b) {
-    release();
-    if (b == 0) return;
-    HIP_CHECK(hipMalloc(&p, b));
-    bytes = b;
-  }
+  inline void release();
+  inline void alloc(size_t b);
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
+
+// Device memory kept for reuse by the factorizations of one tree: blocks that
+// a freed factorization gave back are handed out again, best fit among those
+// at most twice the request.  Shared by the tree and its factorizations and
+// released with the last of them; a failed hipMalloc first releases the kept
+// blocks and retries.
+struct MemPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> kept;
+  ~MemPool() { trim(); }
+  void* take(size_t b, size_t* cap) {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      auto it = kept.lower_bound(b);
+      if (it != kept.end() && it->first / 2 <= b) {
+        *cap = it->first;
+        void* p = it->second;
+        kept.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      HIP_CHECK(hipMalloc(&p, b));
+    }
+    *cap = b;
+    return p;
+  }
+  void give(void* p, size_t cap) {
+    std::lock_guard<std::mutex> g(mu);
+    kept.emplace(cap, p);
+  }
+  void trim() {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& kv : kept) (void)hipFree(kv.second);
+    kept.clear();
+  }
+};
+
+inline void DevMem::release() {
+  if (p) {
+    if (pool) pool->give(p, cap);
+    else (void)hipFree(p);
+  }
+  p = nullptr;
+  bytes = cap = 0;
+}
+
+inline void DevMem::alloc(size_t b) {
+  release();
+  if (b == 0) return;
+  if (pool) {
+    p = pool->take(b, &cap);
+  } else {
+    HIP_CHECK(hipMalloc(&p, b));
+    cap = b;
+  }
+  bytes = b;
+}
 
 // Page-locked host memory (asynchronous device-to-host copies).
 struct PinnedMem {
@@ -101,12 +160,14 @@ struct PinnedMem {
 struct Arena {
   std::vector<DevMem> chunks;
   size_t used = 0;
+  MemPool* pool = nullptr;
   static constexpr size_t kChunk = size_t(256) << 20;
   void* alloc(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
     if (chunks.empty() || used + bytes > chunks.back().bytes) {
       DevMem m;
+      m.pool = pool;
       m.alloc(std::max(bytes, kChunk));
       chunks.push_back(std::move(m));
       used = 0;
@@ -130,12 +191,15 @@ struct Arena {
 struct SweepSet {
   std::vector<PackDev> ph;
   std::vector<int2> up_h[2], down_h;
+  std::vector<int2> upf_h[2], downf_h;   // whole-front items (front, 0)
   int64_t pk_elems = 0, pt_elems = 0, dv_elems = 0;
   int kup = 0, kdown = 0;            // rows of x one work-group stages at most
   double fac[2] = {0, 0}, srows[2] = {0, 0}, prows[2] = {0, 0};
   PackDev* packs = nullptr;
   int2* up[2] = {nullptr, nullptr};
   int2* down = nullptr;
+  int2* upf[2] = {nullptr, nullptr};
+  int2* downf = nullptr;
 };
 
 // Work lists and per-color work of the fronts in S.ph (colors[i] per front).
@@ -143,6 +207,9 @@ static void sweep_items(SweepSet& S, const std::vector<int>& colors) {
   S.up_h[0].clear();
   S.up_h[1].clear();
   S.down_h.clear();
+  S.upf_h[0].clear();
+  S.upf_h[1].clear();
+  S.downf_h.clear();
   S.kup = S.kdown = 0;
   for (int c = 0; c < 2; ++c) S.fac[c] = S.srows[c] = S.prows[c] = 0;
   for (size_t fi = 0; fi < S.ph.size(); ++fi) {
@@ -155,6 +222,10 @@ static void sweep_items(SweepSet& S, const std::vector<int>& colors) {
     }
     for (int t = 0; t < P16; t += kSwWaves) S.down_h.push_back(make_int2(int(fi), t));
     S.kdown = std::max(S.kdown, 16 * rt);
+    if (P16 > 0) {
+      S.upf_h[c].push_back(make_int2(int(fi), 0));
+      S.downf_h.push_back(make_int2(int(fi), 0));
+    }
     S.fac[c] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
     S.srows[c] += f.s;
     S.prows[c] += f.p;
@@ -194,6 +265,9 @@ static void upload_sweep(SweepSet& S, Arena& mem, hipStream_t st) {
   S.up[0] = mem.upload(S.up_h[0], st);
   S.up[1] = mem.upload(S.up_h[1], st);
   S.down = mem.upload(S.down_h, st);
+  S.upf[0] = mem.upload(S.upf_h[0], st);
+  S.upf[1] = mem.upload(S.upf_h[1], st);
+  S.downf = mem.upload(S.downf_h, st);
 }
 
 // Device description of the cells of one level; depends on the plan only, so
@@ -270,6 +344,20 @@ struct GroupLevel {
 using namespace hifde;
 
 struct hifde_tree_s {
+  std::shared_ptr<MemPool> pool = std::make_shared<MemPool>();   // factorizations' memory
+  std::mutex scratch_mu;                                         // planners' working arrays
+  std::vector<std::unique_ptr<PlanScratch>> scratch;
+  std::unique_ptr<PlanScratch> take_scratch() {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (scratch.empty()) return nullptr;
+    auto s = std::move(scratch.back());
+    scratch.pop_back();
+    return s;
+  }
+  void give_scratch(std::unique_ptr<PlanScratch> s) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    scratch.push_back(std::move(s));
+  }
   Geom g;
   std::map<uint64_t, int> tune;             // autotuner choices (see tune_choice)
   std::vector<float> model;                 // rank predictor weights (host)
@@ -281,6 +369,8 @@ struct hifde_tree_s {
 };
 
 struct hifde_factor_s {
+  // declared first: released after every member that allocated from it
+  std::shared_ptr<MemPool> pool;
   Geom g;
   hifde_precision prec = HIFDE_FP64;
   double eps = 0.0;
@@ -310,6 +400,7 @@ struct hifde_factor_s {
   // sizes), 1 = bounded by the rank model's predictions, 2 = worst case
   int presize = 0;
   hipStream_t aux = nullptr;               // rank-model inference
+  hipStream_t side = nullptr;              // apply forms and packing of the cells
   hipEvent_t offd_ev = nullptr;            // stencil ready (for aux)
   const float* model = nullptr;            // device weights (tree-owned)
   std::vector<hipEvent_t> events;          // created here, destroyed with F
@@ -324,22 +415,53 @@ struct hifde_factor_s {
   hipGraphExec_t gexec = nullptr;
   int g_nrhs = 0;
   const void *g_x = nullptr, *g_z = nullptr;
+  // The side stream, after the work queued on st so far.
+  hipStream_t side_after(hipStream_t st) {
+    if (!side) HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    hipEvent_t e = new_event();
+    HIP_CHECK(hipEventRecord(e, st));
+    HIP_CHECK(hipStreamWaitEvent(side, e, 0));
+    return side;
+  }
+  // Later work on st waits for the side stream's.
+  void join_side(hipStream_t st) {
+    if (!side) return;
+    hipEvent_t e = new_event();
+    HIP_CHECK(hipEventRecord(e, side));
+    HIP_CHECK(hipStreamWaitEvent(st, e, 0));
+  }
   hipEvent_t new_event() {
     hipEvent_t e = nullptr;
     HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     events.push_back(e);
     return e;
   }
-  ~hifde_factor_s() {
+  void use_pool(std::shared_ptr<MemPool> p) {
+    pool = std::move(p);
+    for (DevMem* m : {&diag, &offd, &X, &Z, &pcg}) m->pool = pool.get();
+    mem.pool = pool.get();
+  }
+  // Releases the runtime handles (idempotent).
+  void release_handles() {
+    // blocks go back to the pool for reuse: no kernel may still use them
+    if (pool) (void)hipDeviceSynchronize();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
     if (aux) (void)hipStreamDestroy(aux);
+    aux = nullptr;
+    if (side) (void)hipStreamDestroy(side);
+    side = nullptr;
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
     if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
     for (ProfEvent& e : prof_ev) {
       if (e.a) (void)hipEventDestroy(e.a);
       if (e.b) (void)hipEventDestroy(e.b);
     }
+    prof_ev.clear();
   }
+  ~hifde_factor_s() { release_handles(); }
 };
 
 static thread_local std::string g_last_error;
@@ -441,14 +563,16 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
   return cs;
 }
 
-static void upload_cell_static(CellStatic& cs, hipStream_t st) {
+// Device copies of the descriptors, in `mem` (the tree-shared level-0
+// descriptors keep their own arena; later levels use the factor's).
+static void upload_cell_static(CellStatic& cs, Arena& mem, hipStream_t st) {
   if (cs.on_device) return;
-  cs.fronts = cs.mem.upload(cs.fh, st);
-  cs.srcs = cs.mem.upload(cs.srcs_h, st);
-  cs.maps = cs.mem.upload(*cs.maps_h, st);
-  cs.trips = cs.mem.upload(cs.trips_h, st);
-  cs.idx = cs.mem.upload(cs.idx_h, st);
-  upload_sweep(cs.sw, cs.mem, st);
+  cs.fronts = mem.upload(cs.fh, st);
+  cs.srcs = mem.upload(cs.srcs_h, st);
+  cs.maps = mem.upload(*cs.maps_h, st);
+  cs.trips = mem.upload(cs.trips_h, st);
+  cs.idx = mem.upload(cs.idx_h, st);
+  upload_sweep(cs.sw, mem, st);
   cs.on_device = true;
 }
 
@@ -495,14 +619,14 @@ static std::shared_ptr<GroupStatic> make_group_static(const hifde_factor_s& F,
   return gs;
 }
 
-static void upload_group_static(GroupStatic& gs, hipStream_t st) {
+static void upload_group_static(GroupStatic& gs, Arena& mem, hipStream_t st) {
   if (gs.on_device) return;
-  gs.bfronts = gs.mem.upload(gs.bf, st);
-  gs.maps = gs.mem.upload(*gs.maps_h, st);
-  gs.bsrcs = gs.mem.upload(gs.bsrcs_h, st);
-  gs.btrips = gs.mem.upload(gs.btrips_h, st);
-  gs.gsrcs = gs.mem.upload(gs.gsrcs_h, st);
-  gs.gtrips = gs.mem.upload(gs.gtrips_h, st);
+  gs.bfronts = mem.upload(gs.bf, st);
+  gs.maps = mem.upload(*gs.maps_h, st);
+  gs.bsrcs = mem.upload(gs.bsrcs_h, st);
+  gs.btrips = mem.upload(gs.btrips_h, st);
+  gs.gsrcs = mem.upload(gs.gsrcs_h, st);
+  gs.gtrips = mem.upload(gs.gtrips_h, st);
   gs.on_device = true;
 }
 
@@ -739,7 +863,7 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   }
   if (F.plan_only) return;
   CellStatic& S = *D.st;
-  upload_cell_static(S, st);
+  upload_cell_static(S, l == 0 ? S.mem : F.mem, st);
   D.pool = F.mem.get<T>(size_t(S.elems));
   HIP_CHECK(hipMemsetAsync(D.pool, 0, size_t(S.elems) * sizeof(T), st));
   D.info = F.mem.get<int>(std::max(1, S.ncell));
@@ -779,13 +903,18 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
         batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, v);
       });
   batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, var);
+  // The apply form and its packed copy are read by the sweeps only: they run
+  // on the side stream, beside this level's IDs and the next level's
+  // planning.  They touch the first p columns of each front; the groups and
+  // later levels read the update blocks.
+  hipStream_t ss = F.side_after(st);
   const int ivar = tune_choice(
       F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 2, 1, D.pool,
-      size_t(S.elems) * sizeof(T), st,
-      [&](int v) { apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, st, false, true, v); });
-  apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, st, false, true, ivar);
+      size_t(S.elems) * sizeof(T), ss,
+      [&](int v) { apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v); });
+  apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar);
   pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
-                 &D.dinv, st);
+                 &D.dinv, ss);
 }
 
 static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
@@ -900,7 +1029,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   if (F.plan_only) return;
   const bool pre = skel && F.presize != 0 && G.ngroup > 0;
   if (pre && F.presize == 1) predict_ranks(F, G, l);
-  upload_group_static(S, st);
+  upload_group_static(S, l == 0 ? S.mem : F.mem, st);
   G.base = F.mem.get<T>(size_t(S.base_elems));
   HIP_CHECK(hipMemsetAsync(G.base, 0, size_t(S.base_elems) * sizeof(T), st));
   PoolTable pt_prev = pools_for_level(F, l - 1);
@@ -1414,21 +1543,53 @@ static unsigned interp_chunks(const GroupLevel& G, int nrhs, bool up) {
   return unsigned(ch);
 }
 
+// Whole-front steps (one work-group per front and column chunk) when a
+// launch has at least kSwWholeMin of them and the staged rows fit
+// kSwWholeLds bytes of LDS.
+constexpr int kSwWholeLds = 40 * 1024;
+static int sweep_whole_min() {
+  static const int v = [] {
+    const char* e = std::getenv("HIFDE_SWEEP_WHOLE_MIN");
+    return e ? std::max(1, std::atoi(e)) : 1024;
+  }();
+  return v;
+}
+template <typename T>
+static bool sweep_whole(int nfronts, int nrhs, int rows, SweepShape* g) {
+  const int NT = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4;
+  const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
+  const size_t lds = size_t(rows) * sweep_stride(NT) * sizeof(T);
+  if (int64_t(nfronts) * nch < sweep_whole_min() || lds > size_t(kSwWholeLds)) return false;
+  g->NT = NT;
+  g->nch = nch;
+  g->kch = rows;
+  g->lds = lds;
+  g->grid = unsigned(int64_t(8) * ((nfronts + 7) / 8) * nch);
+  return true;
+}
+
 template <typename T, typename TX>
 static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, int c,
                      const void* pk, const void* dinv, const int32_t* idx, TX* X, TX* Z, int nrhs,
                      hipStream_t st) {
   const int n = int(S.up_h[c].size());
   if (n == 0) return;
-  const SweepShape g = sweep_shape<T>(n, nrhs, S.kup);
+  SweepShape g{};
+  const int nf = int(S.upf_h[c].size());
+  const bool whole = sweep_whole<T>(nf, nrhs, S.kdown, &g);   // all 16 ceil(s/16) rows
+  if (!whole) g = sweep_shape<T>(n, nrhs, S.kup);
   const Work w = F.prof_mask ? sweep_work(S, c, true, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
   const T* P = static_cast<const T*>(pk);
   const T* Dv = static_cast<const T*>(dinv);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
   timed(F, cls, level, w.bytes, w.flops, st, [&] {
 #define HIFDE_UP(NTV, VV)                                                                       \
-  hipLaunchKernelGGL((k_sweep_up<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,       \
-                     S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch)
+  if (whole)                                                                                    \
+    hipLaunchKernelGGL((k_sweep_up_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
+                       S.packs, S.upf[c], nf, g.nch, P, Dv, idx, X, Z, nrhs);                   \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_sweep_up<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,   \
+                       S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch)
     if (vec) {
       if (g.NT == 1) HIFDE_UP(1, true); else if (g.NT == 2) HIFDE_UP(2, true); else HIFDE_UP(4, true);
     } else {
@@ -1443,14 +1604,21 @@ static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S,
                        const int32_t* idx, TX* X, const TX* Z, int nrhs, hipStream_t st) {
   const int n = int(S.down_h.size());
   if (n == 0) return;
-  const SweepShape g = sweep_shape<T>(n, nrhs, S.kdown);
+  SweepShape g{};
+  const int nf = int(S.downf_h.size());
+  const bool whole = sweep_whole<T>(nf, nrhs, S.kdown, &g);
+  if (!whole) g = sweep_shape<T>(n, nrhs, S.kdown);
   const Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
   const T* P = static_cast<const T*>(pt);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
   timed(F, cls, level, w.bytes, w.flops, st, [&] {
-#define HIFDE_DN(NTV, VV)                                                                       \
-  hipLaunchKernelGGL((k_sweep_down<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,     \
-                     S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch)
+#define HIFDE_DN(NTV, VV)                                                                         \
+  if (whole)                                                                                      \
+    hipLaunchKernelGGL((k_sweep_down_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
+                       S.packs, S.downf, nf, g.nch, P, idx, X, Z, nrhs);                          \
+  else                                                                                            \
+    hipLaunchKernelGGL((k_sweep_down<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,   \
+                       S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch)
     if (vec) {
       if (g.NT == 1) HIFDE_DN(1, true); else if (g.NT == 2) HIFDE_DN(2, true); else HIFDE_DN(4, true);
     } else {
@@ -1508,7 +1676,8 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
 // F^-1 application through a HIP graph: the launches of one application
 // (fixed buffers, fixed right-hand-side count) are captured once on a
 // private stream and replayed on the caller's stream.  Timed launches
-// (hifde_profile) and HIFDE_NO_GRAPH use direct launches.
+// (hifde_profile: HIP reports no durations for events recorded inside a
+// graph) and HIFDE_NO_GRAPH use direct launches.
 template <typename T, typename TX>
 static void apply_inverse_g(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t st) {
   if (!F.use_graph || F.prof_mask) {
@@ -1555,31 +1724,32 @@ static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
 // iteration per column, all vectors unknown-major in double; TR is the type
 // of the preconditioner's vectors (float: flexible beta).  Returns whether
 // every column reached tol.
-template <typename TR>
-static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
-                    int64_t ldu, double tol, int maxit, int* iters, double* relres,
-                    hipStream_t st) {
+template <typename TR, int W>
+static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
+                      int64_t ldu, double tol, int maxit, int* iters, double* relres,
+                      hipStream_t st) {
+  using TP = typename std::conditional<sizeof(TR) == 4, float, double>::type;
   const int64_t N = F.g.N, n = N * nrhs;
   const int nr = int(nrhs);
   const int flexible = sizeof(TR) == 4 ? 1 : 0;
-  // vectors: x r p Ap zold (double), partials, scalars
+  // vectors: x r and two p buffers (double), two partial sets, scalars
   const size_t vbytes = size_t(n) * 8;
   const size_t pbytes = size_t(kPcgBlocks) * 2 * nr * 8;
   if (F.pcg_rhs != nrhs) {
-    F.pcg.alloc(vbytes * 5 + pbytes + size_t(nr) * 8 * 8 + size_t(nr) * 4);
+    F.pcg.alloc(vbytes * 4 + pbytes * 2 + size_t(nr) * 8 * 8 + size_t(nr) * 4);
     F.pcg_rhs = nrhs;
   }
   ensure_X(F, nrhs);
-  TR* rc = F.X.as<TR>();          // r copy, turned into z by the sweeps
+  TR* rc = F.X.as<TR>();          // r in the preconditioner's type, turned into z by F^-1
   TR* Zs = F.Z.as<TR>();
   char* base = F.pcg.as<char>();
   double* x = reinterpret_cast<double*>(base);
   double* r = x + n;
-  double* p = r + n;
-  double* Ap = p + n;
-  double* zold = Ap + n;
-  double* partial = zold + n;
-  double* sc = partial + size_t(kPcgBlocks) * 2 * nr;
+  double* pa = r + n;              // p of the last iteration
+  double* pb = pa + n;             // p of this one
+  double* px = pb + n;             // partials of k_pcg_xr
+  double* pz = px + size_t(kPcgBlocks) * 2 * nr;   // partials of k_pcg_ap / k_pcg_rz
+  double* sc = pz + size_t(kPcgBlocks) * 2 * nr;
   double* rz = sc;
   double* alpha = sc + nr;
   double* beta = sc + 2 * nr;
@@ -1588,18 +1758,20 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
   const unsigned nb = kPcgBlocks;
   const int dim = F.g.dim;
   const int64_t side = F.g.n;
+  const DivN dn = make_divn(uint32_t(side));
   const double* diag = F.diag.as<double>();
   const double* offd = F.offd.as<double>();
 
   hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
                      r);
   HIP_CHECK(hipMemsetAsync(x, 0, vbytes, st));
-  HIP_CHECK(hipMemsetAsync(p, 0, vbytes, st));
+  HIP_CHECK(hipMemsetAsync(pa, 0, vbytes, st));
   HIP_CHECK(hipMemsetAsync(alpha, 0, size_t(nr) * 8, st));
-  // ||f||^2 and the preconditioner's copy of r
-  hipLaunchKernelGGL((k_pcg_xr<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, alpha, p, Ap, x, r,
-                     rc, partial);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, partial, d1);
+  HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
+  // ||f||^2 and the preconditioner's copy of r (alpha = 0: x, r unchanged)
+  hipLaunchKernelGGL((k_pcg_xr<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, dim, dn, diag,
+                     offd, alpha, pa, x, r, rc, 0, px);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
   std::vector<int> liveh(nr, 1), itsh(nr, 0);
   std::vector<double> fh(nr), h1(nr);
   HIP_CHECK(hipMemcpyAsync(fh.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
@@ -1609,27 +1781,25 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
     if (fh[c] == 0.0) liveh[c] = 0;
   }
   HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
-  apply_inverse_g<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs,
-                                                                                        nr, st);
-  HIP_CHECK(hipMemsetAsync(zold, 0, vbytes, st));
-  hipLaunchKernelGGL((k_pcg_z<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, zold, 0, partial);
-  HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
-  hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz, live,
-                     beta);
-  hipLaunchKernelGGL(k_pcg_p, dim3(nblk(n)), dim3(kThreads), 0, st, n, nr, beta, live, zold, p);
+  apply_inverse_g<TP, TR>(F, rc, Zs, nr, st);
+  // rz = r.z, beta = 0 (rz was 0)
+  hipLaunchKernelGGL((k_pcg_rz<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, pz);
+  hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, px, 0, rz,
+                     live, beta);
   int it = 0;
   while (it < maxit) {
     bool any = false;
     for (int c = 0; c < nr; ++c) any = any || liveh[c];
     if (!any) break;
     ++it;
-    hipLaunchKernelGGL(k_pcg_ap, dim3(nb), dim3(kThreads), 0, st, N, nr, dim, side, diag, offd, p,
-                       Ap, partial);
-    hipLaunchKernelGGL(k_reduce_alpha, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz,
-                       live, alpha);
-    hipLaunchKernelGGL((k_pcg_xr<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, alpha, p, Ap, x, r,
-                       rc, partial);
-    hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, partial, d1);
+    hipLaunchKernelGGL((k_pcg_ap<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, dim, dn, diag,
+                       offd, beta, rc, pa, pb, pz);
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, rz, live,
+                       alpha);
+    hipLaunchKernelGGL((k_pcg_xr<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, dim, dn, diag,
+                       offd, alpha, pb, x, r, rc, flexible, px);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
+    std::swap(pa, pb);
     HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     bool changed = false, anyl = false;
@@ -1644,21 +1814,18 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
     }
     if (changed) HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
     if (!anyl || it == maxit) break;
-    apply_inverse_g<typename std::conditional<sizeof(TR) == 4, float, double>::type, TR>(F, rc, Zs,
-                                                                                          nr, st);
-    hipLaunchKernelGGL((k_pcg_z<TR>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, zold,
-                       flexible, partial);
-    hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, partial, rz,
-                       live, beta);
-    hipLaunchKernelGGL(k_pcg_p, dim3(nblk(n)), dim3(kThreads), 0, st, n, nr, beta, live, zold, p);
+    apply_inverse_g<TP, TR>(F, rc, Zs, nr, st);
+    hipLaunchKernelGGL((k_pcg_rz<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, pz);
+    hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, px,
+                       flexible, rz, live, beta);
   }
-  // true residuals ||f - A x||
+  // true residuals ||f - A x|| (A x into pb, f into r)
   hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, dim, side, diag, offd,
-                     x, Ap);
+                     x, pb);
   hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
                      r);
-  hipLaunchKernelGGL(k_pcg_resid, dim3(nb), dim3(kThreads), 0, st, N, nr, r, Ap, partial);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, partial, d1);
+  hipLaunchKernelGGL(k_pcg_resid, dim3(nb), dim3(kThreads), 0, st, N, nr, r, pb, px);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
   HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
   hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, x, u, ldu);
   HIP_CHECK(hipGetLastError());
@@ -1672,13 +1839,22 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
   return converged;
 }
 
+template <typename TR>
+static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
+                    int64_t ldu, double tol, int maxit, int* iters, double* relres,
+                    hipStream_t st) {
+  if (nrhs % 2 == 0)
+    return run_pcg_w<TR, 2>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
+  return run_pcg_w<TR, 1>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
+}
+
 // Stencil assembly and the factorization of every level into F.
 static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* const* a,
                          const double* b, double eps, hifde_precision prec, hipStream_t st) {
   F.g = tree->g;
   F.prec = prec;
   F.eps = eps;
-  F.planner.reset(new Planner(F.g));
+  F.planner.reset(new Planner(F.g, tree->take_scratch()));
   F.cl.resize(F.g.L + 1);
   F.gl.resize(F.g.L);
   const int64_t N = F.g.N;
@@ -1703,7 +1879,9 @@ static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* co
   if (badh & 2) throw Error(HIFDE_EINVAL, "b must be finite");
   if (prec == HIFDE_MIXED) run_factor<float>(F, tree, st);
   else run_factor<double>(F, tree, st);
+  F.join_side(st);
   HIP_CHECK(hipStreamSynchronize(st));
+  tree->give_scratch(F.planner->take_scratch());   // planning is over (not after a failure)
 }
 
 // Counts the bytes that differ between two device buffers.
@@ -1778,7 +1956,19 @@ int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels, hifde_tr
 
 void hifde_tree_free(hifde_tree_t tree) { delete tree; }
 
-void hifde_factor_free(hifde_factor_t F) { delete F; }
+void hifde_factor_free(hifde_factor_t F) {
+  if (!F) return;
+  PhaseTimer tm;
+  F->release_handles();
+  tm.mark("free: handles", -1);
+  F->cl.clear();
+  F->gl.clear();
+  tm.mark("free: levels", -1);
+  discard_planner(std::move(F->planner));
+  tm.mark("free: planner", -1);
+  delete F;
+  tm.mark("free: rest", -1);
+}
 
 int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, double eps,
                  hifde_precision prec, uint32_t flags, void* hip_stream, hifde_factor_t* out) {
@@ -1805,6 +1995,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     F->model = presize == 1 ? tree->model_d.as<float>() : nullptr;
     F->autotune = (flags & HIFDE_AUTOTUNE) != 0;
     F->tree = tree;
+    F->use_pool(tree->pool);
     build_factor(*F, tree, a, b, eps, prec, st);
     F->use_graph = !(flags & HIFDE_NO_GRAPH);
     fill_stats(*F);
@@ -1812,6 +2003,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (flags & HIFDE_DEBUG_DETERMINISM) {
       hifde_factor_s F2;
+      F2.use_pool(tree->pool);
       F2.presize = presize;
       F2.model = F->model;
       F2.tree = tree;

@@ -105,6 +105,51 @@ class PlanPool {
   uint64_t epoch_ = 0;
   bool stop_ = false;
 };
+
+// Frees finished planners on a background thread: their level plans are
+// many small host arrays, whose release would otherwise hold up the caller.
+class Janitor {
+ public:
+  static Janitor& get() {
+    static Janitor j;
+    return j;
+  }
+  void discard(std::unique_ptr<Planner> p) {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      q_.push_back(std::move(p));
+    }
+    cv_.notify_one();
+  }
+
+ private:
+  Janitor() : t_([this] { loop(); }) {}
+  ~Janitor() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_one();
+    t_.join();
+  }
+  void loop() {
+    std::unique_lock<std::mutex> lk(m_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+      if (q_.empty()) return;   // stopping, nothing left
+      std::vector<std::unique_ptr<Planner>> batch;
+      batch.swap(q_);
+      lk.unlock();
+      batch.clear();
+      lk.lock();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable cv_;
+  std::vector<std::unique_ptr<Planner>> q_;
+  bool stop_ = false;
+  std::thread t_;   // last: starts once the members above exist
+};
 }  // namespace
 
 // Runs f(i, worker) for i in [0, n) on up to `workers` threads (worker ids
@@ -148,13 +193,23 @@ std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
   return "";
 }
 
-Planner::Planner(const Geom& g) : g_(g) {
+Planner::Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch) : g_(g) {
+  if (scratch) {
+    loc_ = std::move(scratch->loc);
+    own0_ = std::move(scratch->own0);
+    own1_ = std::move(scratch->own1);
+    act_ = std::move(scratch->act);
+    active_ = std::move(scratch->active);
+    grouped_ = std::move(scratch->grouped);
+  }
   active_.assign(g_.N, 1);
   grouped_.assign(g_.N, 0);
   workers_ = PlanPool::get().size();
   loc_.resize(workers_);
-  own0_.assign(g_.N, -1);
-  own1_.assign(g_.N, -1);
+  for (auto& v : loc_)
+    if (!v.empty() && int64_t(v.size()) != g_.N) v.clear();   // re-made on first use
+  if (int64_t(own0_.size()) != g_.N) own0_.assign(g_.N, -1);
+  if (int64_t(own1_.size()) != g_.N) own1_.assign(g_.N, -1);
   act_.resize(g_.N);
   for (int64_t d = 0; d < g_.N; ++d) act_[d] = int32_t(d);
   lv_.resize(g_.L + 1);
@@ -166,6 +221,23 @@ Planner::Planner(const Geom& g) : g_(g) {
       const int64_t M = g_.m << l;
       if ((x + 1) % M == 0 && x != g_.n - 1) seplev_[x] = int8_t(l);
     }
+}
+
+std::unique_ptr<PlanScratch> Planner::take_scratch() {
+  auto s = std::make_unique<PlanScratch>();
+  s->loc = std::move(loc_);
+  s->own0 = std::move(own0_);
+  s->own1 = std::move(own1_);
+  s->act = std::move(act_);
+  s->active = std::move(active_);
+  s->grouped = std::move(grouped_);
+  loc_.clear();
+  own0_.clear();
+  own1_.clear();
+  act_.clear();
+  active_.clear();
+  grouped_.clear();
+  return s;
 }
 
 void Planner::coords(int64_t d, int64_t* x) const {
@@ -600,6 +672,10 @@ void Planner::finish_groups(int l) {
       for (int32_t d : lev.res[gi].rd) active_[d] = 0;
   }
   drop_inactive();
+}
+
+void discard_planner(std::unique_ptr<Planner> p) {
+  if (p) Janitor::get().discard(std::move(p));
 }
 
 }  // namespace hifde

@@ -100,9 +100,20 @@ struct Level {
   }
 };
 
+// Per-unknown working arrays of a planner.  A tree keeps them between its
+// factorizations, so that a planner does not allocate and first-touch them
+// each time; the position maps are all -1 whenever no planning step runs.
+struct PlanScratch {
+  std::vector<std::vector<int32_t>> loc;
+  std::vector<int32_t> own0, own1, act;
+  std::vector<uint8_t> active, grouped;
+};
+
 class Planner {
  public:
-  explicit Planner(const Geom& g);
+  explicit Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch = nullptr);
+  // Hands the working arrays back once planning is over (the levels stay).
+  std::unique_ptr<PlanScratch> take_scratch();
 
   const Geom& geom() const { return g_; }
   // Level l cells (l = L gives the top block).  Requires the groups of
@@ -146,6 +157,9 @@ class Planner {
   std::vector<Level> lv_;
   std::shared_ptr<LevelPlan> building0_;
 };
+
+// Frees a planner on a background thread (host memory only).
+void discard_planner(std::unique_ptr<Planner> p);
 
 // Validates a tree request; returns an empty string when valid.
 std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out);
