@@ -29,11 +29,13 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
-# The kernel the roofline object describes: the upward sweep of F^-1 over
-# cells and skeleton fronts (every launch of k_sweep_up<float, float, 1,
-# true>, the 16-right-hand-side instance: all levels, both cell colors and
-# the groups).
-DOMINANT_KERNEL = "k_sweep_up<float, float, 1, true>"
+# The kernel the roofline object describes: the whole-front upward sweep of
+# F^-1 (every launch of k_sweep_up_f<float, float, 1, true>, the
+# 16-right-hand-side instance: the levels of many fronts, both cell colors
+# and the skeleton fronts there), the kernel with the most time per step.
+# Its launches are exactly those of the profile class
+# HIFDE_PROF_SWEEP_UP_WHOLE.
+DOMINANT_KERNEL = "k_sweep_up_f<float, float, 1, true>"
 DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
 CALIB_COPY_BYTES = 512 << 20
 
@@ -215,12 +217,12 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if profile:
-            H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP, -1)
+            H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP_WHOLE, -1)
         u, its, rel = H.hifde_pcg(F, f_d, tol=1e-12, maxit=200)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if profile:
-            r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP)
+            r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP_WHOLE)
             for k in prof:
                 prof[k] += r[k]
         st = H.hifde_stats(F)

@@ -179,12 +179,18 @@ int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
 enum {
   HIFDE_PROF_SWEEP_UP = 0,    /* upward steps of cells and skeleton fronts:
                                  z_p = D^-1 L^-1 x_p, x_q -= W^T L^-1 x_p
-                                 (Lemma 2.1; Lemma 2.4 after the interpolation) */
-  HIFDE_PROF_SWEEP_DOWN = 1,  /* downward steps: x_p = L^-T (z_p - W x_q)    */
+                                 (Lemma 2.1; Lemma 2.4 after the interpolation),
+                                 launches of the row-tile form               */
+  HIFDE_PROF_SWEEP_DOWN = 1,  /* downward steps: x_p = L^-T (z_p - W x_q),
+                                 row-tile form                               */
   HIFDE_PROF_INTERP = 2,      /* interpolation steps of skeletonized groups:
                                  x_r -= T^T x_s (up), x_s -= T x_r (down)    */
   HIFDE_PROF_TOP = 3,         /* both steps of the top block (double)       */
-  HIFDE_PROF_CLASSES = 4
+  HIFDE_PROF_SWEEP_UP_WHOLE = 4,    /* upward steps, launches of the
+                                       whole-front form (one work-group per
+                                       front: levels of many small fronts)  */
+  HIFDE_PROF_SWEEP_DOWN_WHOLE = 5,  /* downward steps, whole-front form     */
+  HIFDE_PROF_CLASSES = 6
 };
 
 typedef struct {

@@ -37,7 +37,8 @@ HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN = 16, 64
 HIFDE_RANK_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP = 0, 1, 2, 3
-HIFDE_PROF_CLASSES = 4
+HIFDE_PROF_SWEEP_UP_WHOLE, HIFDE_PROF_SWEEP_DOWN_WHOLE = 4, 5
+HIFDE_PROF_CLASSES = 6
 
 
 class HifdeError(RuntimeError):

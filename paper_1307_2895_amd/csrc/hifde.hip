@@ -1582,7 +1582,8 @@ static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, i
   const T* P = static_cast<const T*>(pk);
   const T* Dv = static_cast<const T*>(dinv);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
-  timed(F, cls, level, w.bytes, w.flops, st, [&] {
+  const int pcls = whole && cls == HIFDE_PROF_SWEEP_UP ? HIFDE_PROF_SWEEP_UP_WHOLE : cls;
+  timed(F, pcls, level, w.bytes, w.flops, st, [&] {
 #define HIFDE_UP(NTV, VV)                                                                       \
   if (whole)                                                                                    \
     hipLaunchKernelGGL((k_sweep_up_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
@@ -1611,7 +1612,8 @@ static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S,
   const Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
   const T* P = static_cast<const T*>(pt);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
-  timed(F, cls, level, w.bytes, w.flops, st, [&] {
+  const int pcls = whole && cls == HIFDE_PROF_SWEEP_DOWN ? HIFDE_PROF_SWEEP_DOWN_WHOLE : cls;
+  timed(F, pcls, level, w.bytes, w.flops, st, [&] {
 #define HIFDE_DN(NTV, VV)                                                                         \
   if (whole)                                                                                      \
     hipLaunchKernelGGL((k_sweep_down_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
