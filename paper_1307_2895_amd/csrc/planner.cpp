@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
 #include <condition_variable>
 #include <cstdlib>
 #include <exception>
@@ -18,6 +20,17 @@ namespace hifde {
 // over [0, n), taken `grain` items at a time from an atomic counter; the
 // calling thread works as worker 0.  One job runs at a time.
 namespace {
+// Spins briefly (a waiting thread is usually needed again within a few tens
+// of microseconds while a level is planned) before blocking.
+inline void cpu_relax() {
+#if defined(__x86_64__)
+  __builtin_ia32_pause();
+#else
+  std::this_thread::yield();
+#endif
+}
+constexpr auto kSpin = std::chrono::microseconds(200);
+
 class PlanPool {
  public:
   static PlanPool& get() {
@@ -38,13 +51,17 @@ class PlanPool {
       failed_.store(false);
       err_ = nullptr;
       helpers_ = helpers;
-      pending_ = helpers;
-      ++epoch_;
+      pending_.store(helpers);
+      epoch_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
     work(0);
+    const auto t0 = std::chrono::steady_clock::now();
+    while (pending_.load(std::memory_order_acquire) != 0 &&
+           std::chrono::steady_clock::now() - t0 < kSpin)
+      cpu_relax();
     std::unique_lock<std::mutex> lk(m_);
-    done_.wait(lk, [&] { return pending_ == 0; });
+    done_.wait(lk, [&] { return pending_.load() == 0; });
     fn_ = nullptr;
     if (err_) std::rethrow_exception(err_);
   }
@@ -59,7 +76,7 @@ class PlanPool {
   ~PlanPool() {
     {
       std::lock_guard<std::mutex> lk(m_);
-      stop_ = true;
+      stop_.store(true);
     }
     cv_.notify_all();
     for (auto& t : threads_) t.join();
@@ -80,16 +97,22 @@ class PlanPool {
   void loop(int w) {
     uint64_t seen = 0;
     for (;;) {
+      const auto t0 = std::chrono::steady_clock::now();
+      while (epoch_.load(std::memory_order_acquire) == seen && !stop_.load() &&
+             std::chrono::steady_clock::now() - t0 < kSpin)
+        cpu_relax();
       {
         std::unique_lock<std::mutex> lk(m_);
-        cv_.wait(lk, [&] { return stop_ || epoch_ != seen; });
-        if (stop_) return;
-        seen = epoch_;
+        cv_.wait(lk, [&] { return stop_.load() || epoch_.load() != seen; });
+        if (stop_.load()) return;
+        seen = epoch_.load();
         if (w > helpers_) continue;   // not needed for this job
       }
       work(w);
-      std::lock_guard<std::mutex> lk(m_);
-      if (--pending_ == 0) done_.notify_one();
+      if (pending_.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+        std::lock_guard<std::mutex> lk(m_);
+        done_.notify_one();
+      }
     }
   }
 
@@ -101,9 +124,10 @@ class PlanPool {
   std::atomic<size_t> next_{0};
   std::atomic<bool> failed_{false};
   std::exception_ptr err_;
-  int helpers_ = 0, pending_ = 0;
-  uint64_t epoch_ = 0;
-  bool stop_ = false;
+  int helpers_ = 0;
+  std::atomic<int> pending_{0};
+  std::atomic<uint64_t> epoch_{0};
+  std::atomic<bool> stop_{false};
 };
 
 // Frees finished planners on a background thread: their level plans are
@@ -152,6 +176,22 @@ class Janitor {
 };
 }  // namespace
 
+// Section times of one planning step, printed under HIFDE_TIMING.
+struct PlanTimer {
+  bool on = std::getenv("HIFDE_TIMING") != nullptr;
+  int level;
+  const char* step;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  PlanTimer(const char* s, int l) : level(l), step(s) {}
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[hifde] level %d     %s: %-16s %8.3f ms\n", level, step, what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 // Runs f(i, worker) for i in [0, n) on up to `workers` threads (worker ids
 // below `workers`), `grain` items at a time; the first exception is
 // rethrown here.
@@ -165,6 +205,45 @@ static void parallel_for(size_t n, size_t grain, int workers, F&& f) {
   }
   const std::function<void(size_t, int)> fn = [&](size_t i, int w) { f(i, w); };
   PlanPool::get().run(n, grain, nt, fn);
+}
+
+// Stable grouping of the items i with key[i] >= 0 by key (a counting sort
+// over contiguous blocks of items, so the order inside a key is the items'
+// order): start[k] .. start[k+1] - 1 index `order` for key k.
+static void bucket_by_key(const std::vector<int32_t>& key, int64_t nkey, int workers,
+                          std::vector<int32_t>& start, std::vector<int32_t>& order) {
+  const size_t n = key.size();
+  const size_t nb = std::max<size_t>(1, std::min<size_t>(64, (n + 4095) / 4096));
+  std::vector<int32_t> hist(nb * size_t(nkey), 0);
+  auto range = [&](size_t b, size_t* lo, size_t* hi) {
+    *lo = n * b / nb;
+    *hi = n * (b + 1) / nb;
+  };
+  parallel_for(nb, 1, workers, [&](size_t b, int) {
+    size_t lo, hi;
+    range(b, &lo, &hi);
+    int32_t* h = hist.data() + b * size_t(nkey);
+    for (size_t i = lo; i < hi; ++i)
+      if (key[i] >= 0) ++h[key[i]];
+  });
+  start.assign(size_t(nkey) + 1, 0);
+  for (int64_t k = 0; k < nkey; ++k) {
+    int32_t run = start[k];
+    for (size_t b = 0; b < nb; ++b) {
+      const int32_t c = hist[b * size_t(nkey) + k];
+      hist[b * size_t(nkey) + k] = run;   // this block's first slot for key k
+      run += c;
+    }
+    start[k + 1] = run;
+  }
+  order.resize(size_t(start[nkey]));
+  parallel_for(nb, 1, workers, [&](size_t b, int) {
+    size_t lo, hi;
+    range(b, &lo, &hi);
+    int32_t* h = hist.data() + b * size_t(nkey);
+    for (size_t i = lo; i < hi; ++i)
+      if (key[i] >= 0) order[h[key[i]]++] = int32_t(i);
+  });
 }
 
 std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
@@ -201,6 +280,7 @@ Planner::Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch) : g_(g) {
     act_ = std::move(scratch->act);
     active_ = std::move(scratch->active);
     grouped_ = std::move(scratch->grouped);
+    geo_ = std::move(scratch->geo);
   }
   active_.assign(g_.N, 1);
   grouped_.assign(g_.N, 0);
@@ -221,6 +301,21 @@ Planner::Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch) : g_(g) {
       const int64_t M = g_.m << l;
       if ((x + 1) % M == 0 && x != g_.n - 1) seplev_[x] = int8_t(l);
     }
+  if (int64_t(geo_.size()) != g_.N) {
+    geo_.resize(g_.N);
+    parallel_for(size_t(g_.N), 65536, workers_, [&](size_t d, int) {
+      int64_t x[3];
+      coords(int64_t(d), x);
+      uint32_t v = 0x00FFFFFFu;
+      for (int k = 0; k < g_.dim; ++k) {
+        v &= ~(0xFFu << (8 * k));
+        v |= uint32_t(uint8_t(seplev_[x[k]])) << (8 * k);
+        if (x[k] > 0) v |= 1u << (24 + 2 * k);
+        if (x[k] < g_.n - 1) v |= 2u << (24 + 2 * k);
+      }
+      geo_[d] = v;
+    });
+  }
 }
 
 std::unique_ptr<PlanScratch> Planner::take_scratch() {
@@ -231,6 +326,8 @@ std::unique_ptr<PlanScratch> Planner::take_scratch() {
   s->act = std::move(act_);
   s->active = std::move(active_);
   s->grouped = std::move(grouped_);
+  s->geo = std::move(geo_);
+  geo_.clear();
   loc_.clear();
   own0_.clear();
   own1_.clear();
@@ -247,11 +344,8 @@ void Planner::coords(int64_t d, int64_t* x) const {
 }
 
 int Planner::sigma(int64_t d, int l) const {
-  int64_t x[3];
-  coords(d, x);
-  int s = 0;
-  for (int k = 0; k < g_.dim; ++k) s += seplev_[x[k]] >= l ? 1 : 0;
-  return s;
+  const uint32_t v = geo_[d];
+  return int(int8_t(v) >= l) + int(int8_t(v >> 8) >= l) + int(int8_t(v >> 16) >= l);
 }
 
 int64_t Planner::box_of(int64_t d, int l) const {
@@ -284,11 +378,10 @@ int64_t Planner::group_key(int64_t d, int l) const {
 
 template <class F>
 void Planner::for_neighbors(int64_t d, F&& f) const {
-  int64_t x[3];
-  coords(d, x);
+  const uint32_t b = geo_[d] >> 24;
   for (int k = 0; k < g_.dim; ++k) {
-    if (x[k] > 0) f(d - g_.stride[k], k, /*up=*/false);
-    if (x[k] < g_.n - 1) f(d + g_.stride[k], k, /*up=*/true);
+    if (b & (1u << (2 * k))) f(d - g_.stride[k], k, /*up=*/false);
+    if (b & (2u << (2 * k))) f(d + g_.stride[k], k, /*up=*/true);
   }
 }
 
@@ -342,29 +435,24 @@ void Planner::plan_cells(int l) {
 }
 
 void Planner::build_cells(int l, LevelPlan& lp) {
+  PlanTimer tm("cells", l);
   const bool top = (l == g_.L);
   const int64_t B = top ? 1 : g_.n / (g_.m << l);
   int64_t nbox = 1;
   for (int k = 0; k < g_.dim; ++k) nbox *= B;
   const auto interior = [&](int64_t d) { return top || sigma(d, l) == 0; };
 
-  // Interiors bucketed by box; the ascending scan keeps buckets sorted.
-  std::vector<int32_t> count(nbox + 1, 0);
-  std::vector<int32_t> dofs;
-  std::vector<int32_t> boxes;
+  // Interiors bucketed by box, ascending inside each box.
   std::vector<int32_t> keyv(act_.size());
   parallel_for(act_.size(), 8192, workers_, [&](size_t i, int) {
     const int32_t d = act_[i];
     keyv[i] = interior(d) ? int32_t(box_of(d, l)) : -1;
   });
-  for (size_t i = 0; i < act_.size(); ++i)
-    if (keyv[i] >= 0) {
-      dofs.push_back(act_[i]);
-      boxes.push_back(keyv[i]);
-      ++count[keyv[i] + 1];
-    }
-  for (int64_t b = 0; b < nbox; ++b) count[b + 1] += count[b];
+  tm.mark("keys");
+  std::vector<int32_t> count, order;
+  bucket_by_key(keyv, nbox, workers_, count, order);
   std::vector<int32_t> cell_of_box(nbox, -1);
+  std::vector<int64_t> box_of_cell;
   for (int64_t b = 0; b < nbox; ++b) {
     if (count[b + 1] == count[b]) continue;
     cell_of_box[b] = int32_t(lp.cells.size());
@@ -376,11 +464,17 @@ void Planner::build_cells(int l, LevelPlan& lp) {
       bb /= B;
     }
     c.color = int32_t(par & 1);
-    c.p.reserve(count[b + 1] - count[b]);
     lp.cells.push_back(std::move(c));
+    box_of_cell.push_back(b);
   }
-  for (size_t i = 0; i < dofs.size(); ++i) lp.cells[cell_of_box[boxes[i]]].p.push_back(dofs[i]);
+  parallel_for(lp.cells.size(), 64, workers_, [&](size_t ci, int) {
+    const int64_t b = box_of_cell[ci];
+    std::vector<int32_t>& p = lp.cells[ci].p;
+    p.resize(size_t(count[b + 1] - count[b]));
+    for (int32_t j = count[b]; j < count[b + 1]; ++j) p[size_t(j - count[b])] = act_[order[j]];
+  });
 
+  tm.mark("buckets");
   // Children (level l-1 cells inside each box) and interior bases.
   std::vector<std::vector<int32_t>> kids(lp.cells.size()), gkids(lp.cells.size());
   if (l > 0) {
@@ -407,6 +501,7 @@ void Planner::build_cells(int l, LevelPlan& lp) {
     }
   }
 
+  tm.mark("children");
   // Per cell (independent; maps are collected per cell and concatenated).
   std::vector<std::vector<int32_t>> cmaps(lp.cells.size());
   parallel_for(lp.cells.size(), 8, workers_, [&](size_t ci, int w) {
@@ -470,6 +565,7 @@ void Planner::build_cells(int l, LevelPlan& lp) {
     for (int32_t d : C.p) loc_[d] = -1;
     for (int32_t d : C.q) loc_[d] = -1;
   });
+  tm.mark("fronts");
   lp.maps.resize(concat_offsets(cmaps, [&](size_t i, int64_t base) {
     for (Source& s : lp.cells[i].src) {
       s.rowmap += base;
@@ -480,6 +576,7 @@ void Planner::build_cells(int l, LevelPlan& lp) {
     if (!lp.cells[i].src.empty())
       std::copy(cmaps[i].begin(), cmaps[i].end(), lp.maps.begin() + lp.cells[i].src[0].rowmap);
   });
+  tm.mark("maps");
 }
 
 // ---------------------------------------------------------------------------
@@ -502,42 +599,50 @@ void Planner::plan_groups(int l) {
 }
 
 void Planner::build_groups(int l, LevelPlan& lp) {
+  PlanTimer tm("groups", l);
   const int64_t B = g_.n / (g_.m << l);
   int64_t nkey = g_.dim;
   for (int k = 0; k < g_.dim; ++k) nkey *= B;
-  std::vector<int32_t> count(nkey + 1, 0), keys;
-  std::vector<int32_t> dofs;
   std::vector<int32_t> keyv(act_.size());
   parallel_for(act_.size(), 8192, workers_, [&](size_t i, int) {
     const int32_t d = act_[i];
     keyv[i] = sigma(d, l) == 1 ? int32_t(group_key(d, l)) : -1;
   });
-  for (size_t i = 0; i < act_.size(); ++i)
-    if (keyv[i] >= 0) {
-      dofs.push_back(act_[i]);
-      keys.push_back(keyv[i]);
-      ++count[keyv[i] + 1];
-    }
-  for (int64_t b = 0; b < nkey; ++b) count[b + 1] += count[b];
+  tm.mark("keys");
+  std::vector<int32_t> count, order;
+  bucket_by_key(keyv, nkey, workers_, count, order);
   std::vector<int32_t> group_of_key(nkey, -1);
   for (int64_t b = 0; b < nkey; ++b) {
     if (count[b + 1] == count[b]) continue;
     group_of_key[b] = int32_t(lp.groups.size());
     Group G;
     G.gid = b;
-    G.c.reserve(count[b + 1] - count[b]);
     lp.groups.push_back(std::move(G));
   }
-  for (size_t i = 0; i < dofs.size(); ++i) lp.groups[group_of_key[keys[i]]].c.push_back(dofs[i]);
+  parallel_for(lp.groups.size(), 64, workers_, [&](size_t gi, int) {
+    const int64_t b = lp.groups[gi].gid;
+    std::vector<int32_t>& c = lp.groups[gi].c;
+    c.resize(size_t(count[b + 1] - count[b]));
+    for (int32_t j = count[b]; j < count[b + 1]; ++j) c[size_t(j - count[b])] = act_[order[j]];
+  });
 
+  tm.mark("buckets");
   // Which level-l fronts hold each unknown (at most two).
+  // (in either order: the groups only use the set)
   const auto& cells = lp.cells;
-  for (size_t ci = 0; ci < cells.size(); ++ci)
+  parallel_for(cells.size(), 16, workers_, [&](size_t ci, int) {
     for (int32_t z : cells[ci].q) {
-      if (own0_[z] < 0) own0_[z] = int32_t(ci);
-      else if (own1_[z] < 0) own1_[z] = int32_t(ci);
-      else throw std::runtime_error("planner: unknown in more than two fronts");
+      int32_t expect = -1;
+      if (__atomic_compare_exchange_n(&own0_[z], &expect, int32_t(ci), false, __ATOMIC_RELAXED,
+                                      __ATOMIC_RELAXED))
+        continue;
+      expect = -1;
+      if (!__atomic_compare_exchange_n(&own1_[z], &expect, int32_t(ci), false, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED))
+        throw std::runtime_error("planner: unknown in more than two fronts");
     }
+  });
+  tm.mark("owners");
   // Earlier bases that land in each group.
   std::vector<std::vector<int32_t>> gkids(lp.groups.size());
   if (l > 0) {
@@ -552,6 +657,7 @@ void Planner::build_groups(int l, LevelPlan& lp) {
       gkids[g].push_back(int32_t(gi));
     }
   }
+  tm.mark("children");
   std::vector<std::vector<int32_t>> gm(lp.groups.size());
   parallel_for(lp.groups.size(), 16, workers_, [&](size_t gi, int w) {
     int32_t* loc_ = loc(w);
@@ -626,6 +732,7 @@ void Planner::build_groups(int l, LevelPlan& lp) {
     for (int32_t i = 0; i < nn; ++i) loc_[G.cN[i]] = -1;
     for (int32_t i = 0; i < nc; ++i) loc_[G.c[i]] = -1;
   });
+  tm.mark("groups");
   std::vector<int64_t> gbase(lp.groups.size());
   lp.gmaps.resize(concat_offsets(gm, [&](size_t i, int64_t base) {
     gbase[i] = base;
@@ -642,8 +749,14 @@ void Planner::build_groups(int l, LevelPlan& lp) {
   parallel_for(gm.size(), 64, workers_, [&](size_t i, int) {
     std::copy(gm[i].begin(), gm[i].end(), lp.gmaps.begin() + gbase[i]);
   });
-  for (const Cell& C : cells)
-    for (int32_t z : C.q) own0_[z] = own1_[z] = -1;
+  tm.mark("maps");
+  parallel_for(cells.size(), 16, workers_, [&](size_t ci, int) {
+    for (int32_t z : cells[ci].q) {
+      __atomic_store_n(&own0_[z], -1, __ATOMIC_RELAXED);
+      __atomic_store_n(&own1_[z], -1, __ATOMIC_RELAXED);
+    }
+  });
+  tm.mark("owner reset");
 }
 
 void Planner::set_skeleton(int l, int gi, int k, const int32_t* sk_pos) {

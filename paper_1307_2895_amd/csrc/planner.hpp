@@ -107,6 +107,7 @@ struct PlanScratch {
   std::vector<std::vector<int32_t>> loc;
   std::vector<int32_t> own0, own1, act;
   std::vector<uint8_t> active, grouped;
+  std::vector<uint32_t> geo;    // per unknown, geometry only (see Planner::geo_)
 };
 
 class Planner {
@@ -148,6 +149,9 @@ class Planner {
 
   Geom g_;
   std::vector<int8_t> seplev_;       // highest level at which x is a separator
+  // per unknown d: byte k (k < 3) = seplev_ of coordinate k (-1 beyond dim);
+  // byte 3 bit 2k: x_k > 0, bit 2k+1: x_k < n-1
+  std::vector<uint32_t> geo_;
   std::vector<uint8_t> active_, grouped_;
   std::vector<int32_t> act_;         // sorted active unknowns
   int32_t* loc(int worker);           // worker's global -> local map (all -1)
