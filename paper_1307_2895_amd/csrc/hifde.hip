@@ -667,7 +667,10 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
       maxt = std::max(maxt, T_ * (T_ + 1) / 2);
       maxr = std::max(maxr, (nt + 63) / 64);
     }
-    hipLaunchKernelGGL(k_ldl_diag<T>, dim3(nf), dim3(kThreads), 0, st, pool, fronts_d, j0, info_d);
+    // one wavefront per diagonal block: the 32 dependent steps are latency
+    // bound, so many small work-groups per CU do better than few large ones
+    hipLaunchKernelGGL(k_ldl_diag<T>, dim3(nf), dim3(kDiagThreads), 0, st, pool, fronts_d, j0,
+                       info_d);
     if (maxr > 0) {
       if (maxr > 65535) throw Error(HIFDE_EINVAL, "front too large for the panel grid");
       hipLaunchKernelGGL(k_ldl_rows<T>, dim3(nf, unsigned(maxr)), dim3(kThreads), 0, st, pool,

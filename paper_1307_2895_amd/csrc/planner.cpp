@@ -281,6 +281,8 @@ Planner::Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch) : g_(g) {
     active_ = std::move(scratch->active);
     grouped_ = std::move(scratch->grouped);
     geo_ = std::move(scratch->geo);
+    active0_ = std::move(scratch->active0);
+    act0_ = std::move(scratch->act0);
   }
   active_.assign(g_.N, 1);
   grouped_.assign(g_.N, 0);
@@ -290,8 +292,7 @@ Planner::Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch) : g_(g) {
     if (!v.empty() && int64_t(v.size()) != g_.N) v.clear();   // re-made on first use
   if (int64_t(own0_.size()) != g_.N) own0_.assign(g_.N, -1);
   if (int64_t(own1_.size()) != g_.N) own1_.assign(g_.N, -1);
-  act_.resize(g_.N);
-  for (int64_t d = 0; d < g_.N; ++d) act_[d] = int32_t(d);
+  act_.clear();   // every unknown: filled by the first plan_cells(0) or adopt_level0
   lv_.resize(g_.L + 1);
   // x lies on a level-l separator iff (x+1) mod (m 2^l) == 0 and x != n-1;
   // these sets are nested, so one number per coordinate describes them.
@@ -327,7 +328,11 @@ std::unique_ptr<PlanScratch> Planner::take_scratch() {
   s->active = std::move(active_);
   s->grouped = std::move(grouped_);
   s->geo = std::move(geo_);
+  s->active0 = std::move(active0_);
+  s->act0 = std::move(act0_);
   geo_.clear();
+  active0_.clear();
+  act0_.clear();
   loc_.clear();
   own0_.clear();
   own1_.clear();
@@ -415,15 +420,29 @@ void Planner::drop_inactive() {
 void Planner::adopt_level0(std::shared_ptr<const LevelPlan> p) {
   lv_[0].plan = p;
   lv_[0].res.assign(p->groups.size(), GroupRes{});
+  if (int64_t(active0_.size()) == g_.N) {   // the tree's level 0 seen before
+    active_ = active0_;
+    act_ = act0_;
+    return;
+  }
+  fill_act();
   for (const Cell& C : p->cells)
     for (int32_t d : C.p) active_[d] = 0;
   drop_inactive();
+  active0_ = active_;
+  act0_ = act_;
+}
+
+void Planner::fill_act() {
+  act_.resize(g_.N);
+  for (int64_t d = 0; d < g_.N; ++d) act_[d] = int32_t(d);
 }
 
 // ---------------------------------------------------------------------------
 // Cells of level l
 // ---------------------------------------------------------------------------
 void Planner::plan_cells(int l) {
+  if (l == 0) fill_act();
   auto lp = std::make_shared<LevelPlan>();
   build_cells(l, *lp);
   if (l == 0) building0_ = lp;

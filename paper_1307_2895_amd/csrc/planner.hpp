@@ -108,6 +108,9 @@ struct PlanScratch {
   std::vector<int32_t> own0, own1, act;
   std::vector<uint8_t> active, grouped;
   std::vector<uint32_t> geo;    // per unknown, geometry only (see Planner::geo_)
+  // the active set once the tree's level-0 cells are eliminated
+  std::vector<uint8_t> active0;
+  std::vector<int32_t> act0;
 };
 
 class Planner {
@@ -146,12 +149,15 @@ class Planner {
   void build_cells(int l, LevelPlan& lp);
   void build_groups(int l, LevelPlan& lp);
   void drop_inactive();
+  void fill_act();
 
   Geom g_;
   std::vector<int8_t> seplev_;       // highest level at which x is a separator
   // per unknown d: byte k (k < 3) = seplev_ of coordinate k (-1 beyond dim);
   // byte 3 bit 2k: x_k > 0, bit 2k+1: x_k < n-1
   std::vector<uint32_t> geo_;
+  std::vector<uint8_t> active0_;     // see PlanScratch
+  std::vector<int32_t> act0_;
   std::vector<uint8_t> active_, grouped_;
   std::vector<int32_t> act_;         // sorted active unknowns
   int32_t* loc(int worker);           // worker's global -> local map (all -1)
