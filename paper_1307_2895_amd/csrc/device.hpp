@@ -53,6 +53,7 @@ struct PackDev {
   int64_t offt;
   int64_t dv;
   int64_t idx;
+  int64_t t_off;     // skeleton fronts: interpolation matrix T (k x p, ld k)
   int32_t s, p;
 };
 

@@ -194,6 +194,7 @@ struct SweepSet {
   std::vector<int2> upf_h[2], downf_h;   // whole-front items (front, 0)
   int64_t pk_elems = 0, pt_elems = 0, dv_elems = 0;
   int kup = 0, kdown = 0;            // rows of x one work-group stages at most
+  int kpf = 0;                       // largest 16 ceil(p/16)
   double fac[2] = {0, 0}, srows[2] = {0, 0}, prows[2] = {0, 0};
   PackDev* packs = nullptr;
   int2* up[2] = {nullptr, nullptr};
@@ -210,7 +211,7 @@ static void sweep_items(SweepSet& S, const std::vector<int>& colors) {
   S.upf_h[0].clear();
   S.upf_h[1].clear();
   S.downf_h.clear();
-  S.kup = S.kdown = 0;
+  S.kup = S.kdown = S.kpf = 0;
   for (int c = 0; c < 2; ++c) S.fac[c] = S.srows[c] = S.prows[c] = 0;
   for (size_t fi = 0; fi < S.ph.size(); ++fi) {
     const PackDev& f = S.ph[fi];
@@ -225,6 +226,7 @@ static void sweep_items(SweepSet& S, const std::vector<int>& colors) {
     if (P16 > 0) {
       S.upf_h[c].push_back(make_int2(int(fi), 0));
       S.downf_h.push_back(make_int2(int(fi), 0));
+      S.kpf = std::max(S.kpf, 16 * P16);
     }
     S.fac[c] += 0.5 * double(f.p) * (f.p + 1) + double(f.s - f.p) * f.p;
     S.srows[c] += f.s;
@@ -1304,6 +1306,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       PackDev q = sall.ph[gi];
       q.p = G.gh[gi].nc - G.gh[gi].k;
       q.idx = G.gh[gi].idx;
+      q.t_off = G.gh[gi].t_off;
       W.ph.push_back(q);
     }
     sweep_items(W, std::vector<int>(W.ph.size(), 0));
@@ -1345,6 +1348,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   }
   F.skel_panels += (rmax + kNB - 1) / kNB;
   build_sweep(G.sw, G.ff, false);
+  for (size_t i = 0; i < G.sw.ph.size(); ++i) G.sw.ph[i].t_off = G.gh[G.gsel_h[i]].t_off;
   upload_sweep(G.sw, F.mem, st);
   pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.pt,
                  &G.dinv, st);
@@ -1558,11 +1562,12 @@ static int sweep_whole_min() {
   return v;
 }
 template <typename T>
-static bool sweep_whole(int nfronts, int nrhs, int rows, SweepShape* g) {
+static bool sweep_whole(int nfronts, int nrhs, int rows, SweepShape* g, bool any_count = false) {
   const int NT = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4;
   const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
   const size_t lds = size_t(rows) * sweep_stride(NT) * sizeof(T);
-  if (int64_t(nfronts) * nch < sweep_whole_min() || lds > size_t(kSwWholeLds)) return false;
+  if (nfronts == 0 || lds > size_t(kSwWholeLds)) return false;
+  if (!any_count && int64_t(nfronts) * nch < sweep_whole_min()) return false;
   g->NT = NT;
   g->nch = nch;
   g->kch = rows;
@@ -1571,26 +1576,34 @@ static bool sweep_whole(int nfronts, int nrhs, int rows, SweepShape* g) {
   return true;
 }
 
+// One upward sweep launch over the fronts of color c of S.  With `tpool`
+// (a group level) only the whole-front form with the interpolation fused is
+// tried: returns false when it does not fit, and the caller runs the
+// interpolation and the row-tile form instead.
 template <typename T, typename TX>
-static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, int c,
+static bool sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, int c,
                      const void* pk, const void* dinv, const int32_t* idx, TX* X, TX* Z, int nrhs,
-                     hipStream_t st) {
+                     hipStream_t st, const void* tpool = nullptr, Work extra = Work{0, 0}) {
   const int n = int(S.up_h[c].size());
-  if (n == 0) return;
+  if (n == 0) return true;
   SweepShape g{};
   const int nf = int(S.upf_h[c].size());
-  const bool whole = sweep_whole<T>(nf, nrhs, S.kdown, &g);   // all 16 ceil(s/16) rows
+  const bool whole = sweep_whole<T>(nf, nrhs, S.kdown, &g, tpool != nullptr);
+  if (tpool && !whole) return false;
   if (!whole) g = sweep_shape<T>(n, nrhs, S.kup);
-  const Work w = F.prof_mask ? sweep_work(S, c, true, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
+  Work w = F.prof_mask ? sweep_work(S, c, true, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
+  w.bytes += extra.bytes;
+  w.flops += extra.flops;
   const T* P = static_cast<const T*>(pk);
   const T* Dv = static_cast<const T*>(dinv);
+  const T* Tp = static_cast<const T*>(tpool);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
   const int pcls = whole && cls == HIFDE_PROF_SWEEP_UP ? HIFDE_PROF_SWEEP_UP_WHOLE : cls;
   timed(F, pcls, level, w.bytes, w.flops, st, [&] {
 #define HIFDE_UP(NTV, VV)                                                                       \
   if (whole)                                                                                    \
     hipLaunchKernelGGL((k_sweep_up_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
-                       S.packs, S.upf[c], nf, g.nch, P, Dv, idx, X, Z, nrhs);                   \
+                       S.packs, S.upf[c], nf, g.nch, P, Dv, idx, X, Z, nrhs, Tp);               \
   else                                                                                          \
     hipLaunchKernelGGL((k_sweep_up<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,   \
                        S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch)
@@ -1601,26 +1614,35 @@ static void sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, i
     }
 #undef HIFDE_UP
   });
+  return true;
 }
 
+// One downward sweep launch; `tpool` as in sweep_up (the interpolation
+// follows the step, in the same launch).
 template <typename T, typename TX>
-static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S, const void* pt,
-                       const int32_t* idx, TX* X, const TX* Z, int nrhs, hipStream_t st) {
+static bool sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S, const void* pt,
+                       const int32_t* idx, TX* X, const TX* Z, int nrhs, hipStream_t st,
+                       const void* tpool = nullptr, Work extra = Work{0, 0}) {
   const int n = int(S.down_h.size());
-  if (n == 0) return;
+  if (n == 0) return true;
   SweepShape g{};
   const int nf = int(S.downf_h.size());
-  const bool whole = sweep_whole<T>(nf, nrhs, S.kdown, &g);
+  const int rows = S.kdown + (tpool ? S.kpf : 0);   // staged rows (+ new x_r)
+  const bool whole = sweep_whole<T>(nf, nrhs, rows, &g, tpool != nullptr);
+  if (tpool && !whole) return false;
   if (!whole) g = sweep_shape<T>(n, nrhs, S.kdown);
-  const Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
+  Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
+  w.bytes += extra.bytes;
+  w.flops += extra.flops;
   const T* P = static_cast<const T*>(pt);
+  const T* Tp = static_cast<const T*>(tpool);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
   const int pcls = whole && cls == HIFDE_PROF_SWEEP_DOWN ? HIFDE_PROF_SWEEP_DOWN_WHOLE : cls;
   timed(F, pcls, level, w.bytes, w.flops, st, [&] {
 #define HIFDE_DN(NTV, VV)                                                                         \
   if (whole)                                                                                      \
     hipLaunchKernelGGL((k_sweep_down_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
-                       S.packs, S.downf, nf, g.nch, P, idx, X, Z, nrhs);                          \
+                       S.packs, S.downf, nf, g.nch, P, idx, X, Z, nrhs, Tp);                      \
   else                                                                                            \
     hipLaunchKernelGGL((k_sweep_down<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,   \
                        S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch)
@@ -1631,6 +1653,7 @@ static void sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S,
     }
 #undef HIFDE_DN
   });
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1648,13 +1671,17 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
       sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, S.sw, color, C.pk, C.dinv, S.idx, X, Z, nrhs, st);
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
+      // interpolation and elimination of ř in one launch when the fronts fit
       const Work w = F.prof_mask ? interp_work(G, true, nrhs, esz, xsz) : Work{0, 0};
-      timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_interp_up<T, TX>), dim3(G.nskel, interp_chunks(G, nrhs, true)),
-                           dim3(kThreads), 0, st, G.groups, G.gsel,
-                           static_cast<const T*>(G.tpool), G.idx, X, nrhs);
-      });
-      sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, G.sw, 0, G.pk, G.dinv, G.idx, X, Z, nrhs, st);
+      if (!sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, G.sw, 0, G.pk, G.dinv, G.idx, X, Z, nrhs,
+                           st, G.tpool, w)) {
+        timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
+          hipLaunchKernelGGL((k_interp_up<T, TX>), dim3(G.nskel, interp_chunks(G, nrhs, true)),
+                             dim3(kThreads), 0, st, G.groups, G.gsel,
+                             static_cast<const T*>(G.tpool), G.idx, X, nrhs);
+        });
+        sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, G.sw, 0, G.pk, G.dinv, G.idx, X, Z, nrhs, st);
+      }
     }
   }
   CellLevel& top = F.cl[L];
@@ -1664,13 +1691,16 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
   for (int l = L - 1; l >= 0; --l) {
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
-      sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pt, G.idx, X, Z, nrhs, st);
       const Work w = F.prof_mask ? interp_work(G, false, nrhs, esz, xsz) : Work{0, 0};
-      timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
-        hipLaunchKernelGGL((k_interp_down<T, TX>), dim3(G.nskel, interp_chunks(G, nrhs, false)),
-                           dim3(kThreads), 0, st, G.groups, G.gsel,
-                           static_cast<const T*>(G.tpool), G.idx, X, nrhs);
-      });
+      if (!sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pt, G.idx, X, Z, nrhs, st,
+                             G.tpool, w)) {
+        sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, G.sw, G.pt, G.idx, X, Z, nrhs, st);
+        timed(F, HIFDE_PROF_INTERP, l, w.bytes, w.flops, st, [&] {
+          hipLaunchKernelGGL((k_interp_down<T, TX>), dim3(G.nskel, interp_chunks(G, nrhs, false)),
+                             dim3(kThreads), 0, st, G.groups, G.gsel,
+                             static_cast<const T*>(G.tpool), G.idx, X, nrhs);
+        });
+      }
     }
     CellLevel& C = F.cl[l];
     sweep_down<T, TX>(F, HIFDE_PROF_SWEEP_DOWN, l, C.st->sw, C.pt, C.st->idx, X, Z, nrhs, st);
