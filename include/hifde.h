@@ -74,9 +74,13 @@ enum {
                                    default the launches of one application
                                    are captured once per right-hand-side
                                    count into a HIP graph and replayed      */
-  HIFDE_PRESIZE_WORST_CASE = 64u /* as HIFDE_USE_RANK_MODEL with every rank
+  HIFDE_PRESIZE_WORST_CASE = 64u, /* as HIFDE_USE_RANK_MODEL with every rank
                                    assumed 0 (the largest possible fronts):
                                    the comparison point of the predictor    */
+  HIFDE_SWEEP_ROW_TILES = 128u  /* F^-1 sweeps in the row-tile form only (no
+                                   whole-front launches, interpolation as
+                                   separate launches); the results are
+                                   bitwise the same                         */
 };
 
 /* Maximum number of tree levels reported by hifde_stats. */

@@ -20,6 +20,7 @@ HIFDE_OK, HIFDE_EINVAL, HIFDE_ENOMEM, HIFDE_EDEVICE, HIFDE_ENOTSPD, HIFDE_ENOCON
 HIFDE_FP64, HIFDE_MIXED = 0, 1
 HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_AUTOTUNE, HIFDE_NO_GRAPH = 1, 4, 8, 16
 HIFDE_PRESIZE_WORST_CASE = 64
+HIFDE_SWEEP_ROW_TILES = 128
 HIFDE_MAX_LEVELS = 24
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD",

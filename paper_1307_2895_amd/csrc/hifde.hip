@@ -413,6 +413,7 @@ struct hifde_factor_s {
   double rank_abs_err = 0;
   // captured F^-1 application (one per right-hand-side count and buffers)
   bool use_graph = true;
+  bool row_tiles = false;                  // HIFDE_SWEEP_ROW_TILES
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_nrhs = 0;
@@ -1588,7 +1589,7 @@ static bool sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, i
   if (n == 0) return true;
   SweepShape g{};
   const int nf = int(S.upf_h[c].size());
-  const bool whole = sweep_whole<T>(nf, nrhs, S.kdown, &g, tpool != nullptr);
+  const bool whole = !F.row_tiles && sweep_whole<T>(nf, nrhs, S.kdown, &g, tpool != nullptr);
   if (tpool && !whole) return false;
   if (!whole) g = sweep_shape<T>(n, nrhs, S.kup);
   Work w = F.prof_mask ? sweep_work(S, c, true, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
@@ -1628,7 +1629,7 @@ static bool sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S,
   SweepShape g{};
   const int nf = int(S.downf_h.size());
   const int rows = S.kdown + (tpool ? S.kpf : 0);   // staged rows (+ new x_r)
-  const bool whole = sweep_whole<T>(nf, nrhs, rows, &g, tpool != nullptr);
+  const bool whole = !F.row_tiles && sweep_whole<T>(nf, nrhs, rows, &g, tpool != nullptr);
   if (tpool && !whole) return false;
   if (!whole) g = sweep_shape<T>(n, nrhs, S.kdown);
   Work w = F.prof_mask ? sweep_work(S, -1, false, nrhs, sizeof(T), sizeof(TX)) : Work{0, 0};
@@ -2013,7 +2014,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
   if (!(eps >= 0.0 && eps < 1.0)) return fail(HIFDE_EINVAL, "eps must lie in [0, 1)");
   if (prec != HIFDE_FP64 && prec != HIFDE_MIXED) return fail(HIFDE_EINVAL, "unknown precision");
   if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_AUTOTUNE |
-                        HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE))
+                        HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE | HIFDE_SWEEP_ROW_TILES))
     return fail(HIFDE_EINVAL, "unknown flags");
   if ((flags & HIFDE_USE_RANK_MODEL) && (flags & HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "HIFDE_USE_RANK_MODEL and HIFDE_PRESIZE_WORST_CASE exclude each other");
@@ -2033,6 +2034,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     F->use_pool(tree->pool);
     build_factor(*F, tree, a, b, eps, prec, st);
     F->use_graph = !(flags & HIFDE_NO_GRAPH);
+    F->row_tiles = (flags & HIFDE_SWEEP_ROW_TILES) != 0;
     fill_stats(*F);
     F->stats.factor_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

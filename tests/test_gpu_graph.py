@@ -74,3 +74,26 @@ def test_unknown_flags_rejected():
     with pytest.raises(H.HifdeError) as ei:
         H.hifde_factor(T, torch_inputs(a), None, 1e-6, 0, flags=1 << 20)
     assert ei.value.code == H.HIFDE_EINVAL
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nrhs", [1, 16, 40])
+def test_whole_front_sweeps_match_row_tiles(prec, nrhs):
+    """The whole-front sweeps (one work-group per front, interpolation fused
+    into the skeleton fronts' launches) take the same products in the same
+    order as the row-tile forms with separate interpolation launches, so
+    F^-1 f must agree bit for bit.  n = 512, leaf 8: 2048 cells per color,
+    enough for the whole-front cell launches."""
+    import paper_1307_2895_amd as H
+    print(f"case prec={prec} nrhs={nrhs}", flush=True)
+    dim, n, m = 2, 512, 8
+    a = W.make_field(dim, n, "bernoulli_contrast", 7)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    Fw = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+    Fr = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec, flags=H.HIFDE_SWEEP_ROW_TILES)
+    f = torch.from_numpy(W.make_rhs(n ** dim, nrhs, 8)).cuda()
+    uw = H.hifde_solve(Fw, f)
+    ur = H.hifde_solve(Fr, f)
+    torch.cuda.synchronize()
+    assert torch.isfinite(uw).all()
+    assert torch.equal(uw, ur)
