@@ -1760,7 +1760,7 @@ static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
 // iteration per column, all vectors unknown-major in double; TR is the type
 // of the preconditioner's vectors (float: flexible beta).  Returns whether
 // every column reached tol.
-template <typename TR, int W>
+template <typename TR, int W, int DIM>
 static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
                       int64_t ldu, double tol, int maxit, int* iters, double* relres,
                       hipStream_t st) {
@@ -1805,7 +1805,7 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   HIP_CHECK(hipMemsetAsync(alpha, 0, size_t(nr) * 8, st));
   HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
   // ||f||^2 and the preconditioner's copy of r (alpha = 0: x, r unchanged)
-  hipLaunchKernelGGL((k_pcg_xr<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, dim, dn, diag,
+  hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb), dim3(kThreads), 0, st, N, nr, dn, diag,
                      offd, alpha, pa, x, r, rc, 0, px);
   hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
   std::vector<int> liveh(nr, 1), itsh(nr, 0);
@@ -1828,11 +1828,11 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
     for (int c = 0; c < nr; ++c) any = any || liveh[c];
     if (!any) break;
     ++it;
-    hipLaunchKernelGGL((k_pcg_ap<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, dim, dn, diag,
+    hipLaunchKernelGGL((k_pcg_ap<TR, W, DIM>), dim3(nb), dim3(kThreads), 0, st, N, nr, dn, diag,
                        offd, beta, rc, pa, pb, pz);
     hipLaunchKernelGGL(k_reduce_alpha, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, rz, live,
                        alpha);
-    hipLaunchKernelGGL((k_pcg_xr<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, dim, dn, diag,
+    hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb), dim3(kThreads), 0, st, N, nr, dn, diag,
                        offd, alpha, pb, x, r, rc, flexible, px);
     hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
     std::swap(pa, pb);
@@ -1879,9 +1879,12 @@ template <typename TR>
 static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
                     int64_t ldu, double tol, int maxit, int* iters, double* relres,
                     hipStream_t st) {
-  if (nrhs % 2 == 0)
-    return run_pcg_w<TR, 2>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
-  return run_pcg_w<TR, 1>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
+  const bool even = nrhs % 2 == 0;
+  if (F.g.dim == 2)
+    return even ? run_pcg_w<TR, 2, 2>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st)
+                : run_pcg_w<TR, 1, 2>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
+  return even ? run_pcg_w<TR, 2, 3>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st)
+              : run_pcg_w<TR, 1, 3>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
 }
 
 // Stencil assembly and the factorization of every level into F.
