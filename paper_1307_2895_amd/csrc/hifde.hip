@@ -414,6 +414,8 @@ struct hifde_factor_s {
   // captured F^-1 application (one per right-hand-side count and buffers)
   bool use_graph = true;
   bool row_tiles = false;                  // HIFDE_SWEEP_ROW_TILES
+  int* bad_d = nullptr;                    // k_stencil's input flags
+  bool input_checked = false;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_nrhs = 0;
@@ -870,8 +872,10 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   if (F.plan_only) return;
   CellStatic& S = *D.st;
   upload_cell_static(S, l == 0 ? S.mem : F.mem, st);
-  D.pool = F.mem.get<T>(size_t(S.elems));
-  HIP_CHECK(hipMemsetAsync(D.pool, 0, size_t(S.elems) * sizeof(T), st));
+  if (!D.pool) {   // (level 0 of a known tree: allocated and cleared up front)
+    D.pool = F.mem.get<T>(size_t(S.elems));
+    HIP_CHECK(hipMemsetAsync(D.pool, 0, size_t(S.elems) * sizeof(T), st));
+  }
   D.info = F.mem.get<int>(std::max(1, S.ncell));
   HIP_CHECK(hipMemsetAsync(D.info, 0, sizeof(int) * std::max(1, S.ncell), st));
   PoolTable pt = pools_for_level(F, l - 1);
@@ -921,6 +925,17 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar);
   pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
                  &D.dinv, ss);
+}
+
+// The input flags of k_stencil (read once, at the first synchronization).
+static void check_input(hifde_factor_s& F, hipStream_t st) {
+  if (F.input_checked || !F.bad_d) return;
+  int h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, F.bad_d, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  F.input_checked = true;
+  if (h & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
+  if (h & 2) throw Error(HIFDE_EINVAL, "b must be finite");
 }
 
 static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
@@ -1247,6 +1262,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   PhaseTimer tw;
   HIP_CHECK(hipStreamSynchronize(st));
   tw.mark("  wait for IDs", l);
+  check_input(F, st);
   // record skeletons; build the skeleton fronts
   int64_t fg_off = 0;
   G.gsel_h.clear();
@@ -1360,6 +1376,12 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   const int L = F.g.L;
   Planner& P = *F.planner;
   PhaseTimer tm;
+  // the level-0 frontal matrices of a known tree are cleared first, so the
+  // device does that while the host adopts the level-0 plan
+  if (tree->l0 && tree->c0 && !F.plan_only) {
+    F.cl[0].pool = F.mem.get<T>(size_t(tree->c0->elems));
+    HIP_CHECK(hipMemsetAsync(F.cl[0].pool, 0, size_t(tree->c0->elems) * sizeof(T), st));
+  }
   // Level 0 and its groups depend on the geometry only: plan once per tree.
   if (!tree->l0) {
     P.plan_cells(0);
@@ -1380,6 +1402,7 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   cells_level<double, T>(F, tree, L, st);
   tm.mark("top", L);
   if (F.plan_only) return;
+  check_input(F, st);
   // pivot checks of every level at once (one synchronization)
   for (int l = 0; l <= L; ++l) {
     check_info(F.cl[l].info, F.cl[l].st->fh.size(), l == L ? "top block" : "cell", l, st);
@@ -1911,15 +1934,15 @@ static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* co
     F.offd_ev = F.new_event();
     HIP_CHECK(hipEventRecord(F.offd_ev, st));
   }
-  int badh = 0;
-  HIP_CHECK(hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipStreamSynchronize(st));
-  if (badh & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
-  if (badh & 2) throw Error(HIFDE_EINVAL, "b must be finite");
+  // the flags are read at the first synchronization of the factorization
+  // (check_input): until then every kernel indexes by structure only, so
+  // invalid values cannot make one fault
+  F.bad_d = bad;
   if (prec == HIFDE_MIXED) run_factor<float>(F, tree, st);
   else run_factor<double>(F, tree, st);
   F.join_side(st);
   HIP_CHECK(hipStreamSynchronize(st));
+  check_input(F, st);
   tree->give_scratch(F.planner->take_scratch());   // planning is over (not after a failure)
 }
 

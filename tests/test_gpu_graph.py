@@ -97,3 +97,32 @@ def test_whole_front_sweeps_match_row_tiles(prec, nrhs):
     torch.cuda.synchronize()
     assert torch.isfinite(uw).all()
     assert torch.equal(uw, ur)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("what", ["a_negative", "a_nan", "b_inf"])
+def test_invalid_coefficients_rejected(prec, what):
+    """Invalid coefficients are reported as HIFDE_EINVAL; the flags k_stencil
+    sets are read at the factorization's first synchronization, after the
+    level-0 kernels have run on the values (they index by structure only)."""
+    import paper_1307_2895_amd as H
+    print(f"case prec={prec} {what}", flush=True)
+    dim, n, m = 2, 64, 8
+    a = W.make_field(dim, n, "loguniform", 11)
+    b = None
+    if what == "a_negative":
+        a[0].flat[5] = -1.0
+    elif what == "a_nan":
+        a[1].flat[7] = np.nan
+    T = H.hifde_build_tree(dim, n, m, 0)
+    args = torch_inputs(a)
+    if what == "b_inf":
+        bb = np.zeros(n ** dim)
+        bb[3] = np.inf
+        b = torch.from_numpy(bb).cuda()
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_factor(T, args, b, 1e-6, prec)
+    assert ei.value.code == H.HIFDE_EINVAL
+    # the tree stays usable
+    F = H.hifde_factor(T, torch_inputs(W.make_field(dim, n, "loguniform", 11)), None, 1e-6, prec)
+    assert H.hifde_stats(F)["top_size"] > 0
