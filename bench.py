@@ -30,12 +30,11 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 # The kernel the roofline object describes: the whole-front upward sweep of
-# F^-1 (every launch of k_sweep_up_f<float, float, 1, true>, the
-# 16-right-hand-side instance: the levels of many fronts, both cell colors
-# and the skeleton fronts there), the kernel with the most time per step.
-# Its launches are exactly those of the profile class
-# HIFDE_PROF_SWEEP_UP_WHOLE.
-DOMINANT_KERNEL = "k_sweep_up_f<float, float, 1, true>"
+# F^-1 over cells (every launch of k_sweep_up_f<float, float, 1, true,
+# false>, the 16-right-hand-side instance: both colors of the levels with
+# many cells), the kernel with the most time per step.  Its launches are
+# exactly those of the profile class HIFDE_PROF_SWEEP_UP_WHOLE.
+DOMINANT_KERNEL = "k_sweep_up_f<float, float, 1, true, false>"
 DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
 CALIB_COPY_BYTES = 512 << 20
 

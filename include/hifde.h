@@ -194,7 +194,12 @@ enum {
                                        whole-front form (one work-group per
                                        front: levels of many small fronts)  */
   HIFDE_PROF_SWEEP_DOWN_WHOLE = 5,  /* downward steps, whole-front form     */
-  HIFDE_PROF_CLASSES = 6
+  HIFDE_PROF_GROUP_UP = 6,    /* upward steps of skeleton fronts with their
+                                 interpolation x_r -= T^T x_s in the same
+                                 launch (whole-front form of groups)        */
+  HIFDE_PROF_GROUP_DOWN = 7,  /* downward steps of skeleton fronts with
+                                 x_s -= T x_r in the same launch            */
+  HIFDE_PROF_CLASSES = 8
 };
 
 typedef struct {

@@ -1622,12 +1622,16 @@ static bool sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, i
   const T* Dv = static_cast<const T*>(dinv);
   const T* Tp = static_cast<const T*>(tpool);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
-  const int pcls = whole && cls == HIFDE_PROF_SWEEP_UP ? HIFDE_PROF_SWEEP_UP_WHOLE : cls;
+  const int pcls = !whole || cls != HIFDE_PROF_SWEEP_UP ? cls
+                   : tpool ? HIFDE_PROF_GROUP_UP : HIFDE_PROF_SWEEP_UP_WHOLE;
   timed(F, pcls, level, w.bytes, w.flops, st, [&] {
-#define HIFDE_UP(NTV, VV)                                                                       \
-  if (whole)                                                                                    \
-    hipLaunchKernelGGL((k_sweep_up_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
-                       S.packs, S.upf[c], nf, g.nch, P, Dv, idx, X, Z, nrhs, Tp);               \
+#define HIFDE_UP(NTV, VV)                                                                         \
+  if (whole && tpool)                                                                             \
+    hipLaunchKernelGGL((k_sweep_up_f<T, TX, NTV, VV, true>), dim3(g.grid), dim3(kThreads), g.lds, \
+                       st, S.packs, S.upf[c], nf, g.nch, P, Dv, idx, X, Z, nrhs, Tp);             \
+  else if (whole)                                                                                 \
+    hipLaunchKernelGGL((k_sweep_up_f<T, TX, NTV, VV, false>), dim3(g.grid), dim3(kThreads), g.lds, \
+                       st, S.packs, S.upf[c], nf, g.nch, P, Dv, idx, X, Z, nrhs, Tp);             \
   else                                                                                          \
     hipLaunchKernelGGL((k_sweep_up<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,   \
                        S.packs, S.up[c], n, g.nch, P, Dv, idx, X, Z, nrhs, g.kch)
@@ -1661,12 +1665,16 @@ static bool sweep_down(hifde_factor_s& F, int cls, int level, const SweepSet& S,
   const T* P = static_cast<const T*>(pt);
   const T* Tp = static_cast<const T*>(tpool);
   const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
-  const int pcls = whole && cls == HIFDE_PROF_SWEEP_DOWN ? HIFDE_PROF_SWEEP_DOWN_WHOLE : cls;
+  const int pcls = !whole || cls != HIFDE_PROF_SWEEP_DOWN ? cls
+                   : tpool ? HIFDE_PROF_GROUP_DOWN : HIFDE_PROF_SWEEP_DOWN_WHOLE;
   timed(F, pcls, level, w.bytes, w.flops, st, [&] {
-#define HIFDE_DN(NTV, VV)                                                                         \
-  if (whole)                                                                                      \
-    hipLaunchKernelGGL((k_sweep_down_f<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
-                       S.packs, S.downf, nf, g.nch, P, idx, X, Z, nrhs, Tp);                      \
+#define HIFDE_DN(NTV, VV)                                                                           \
+  if (whole && tpool)                                                                               \
+    hipLaunchKernelGGL((k_sweep_down_f<T, TX, NTV, VV, true>), dim3(g.grid), dim3(kThreads), g.lds, \
+                       st, S.packs, S.downf, nf, g.nch, P, idx, X, Z, nrhs, Tp);                    \
+  else if (whole)                                                                                   \
+    hipLaunchKernelGGL((k_sweep_down_f<T, TX, NTV, VV, false>), dim3(g.grid), dim3(kThreads),      \
+                       g.lds, st, S.packs, S.downf, nf, g.nch, P, idx, X, Z, nrhs, Tp);            \
   else                                                                                            \
     hipLaunchKernelGGL((k_sweep_down<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st,   \
                        S.packs, S.down, n, g.nch, P, idx, X, Z, nrhs, g.kch)
