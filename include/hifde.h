@@ -199,7 +199,12 @@ enum {
                                  launch (whole-front form of groups)        */
   HIFDE_PROF_GROUP_DOWN = 7,  /* downward steps of skeleton fronts with
                                  x_s -= T x_r in the same launch            */
-  HIFDE_PROF_CLASSES = 8
+  HIFDE_PROF_SWEEP_UP_ONE = 8,   /* upward steps of the level-0 cells, both
+                                    colors in one whole-front launch; the
+                                    x_q updates go to a contribution buffer */
+  HIFDE_PROF_CONTRIB_ADD = 9,    /* x_q -= the contributions of that launch,
+                                    in color order                          */
+  HIFDE_PROF_CLASSES = 10
 };
 
 typedef struct {

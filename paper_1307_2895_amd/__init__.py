@@ -19,7 +19,8 @@ from ._lib import (  # noqa: F401
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
     HIFDE_PROF_SWEEP_UP_WHOLE, HIFDE_PROF_SWEEP_DOWN_WHOLE, HIFDE_PROF_GROUP_UP,
-    HIFDE_PROF_GROUP_DOWN, HIFDE_PROF_CLASSES, HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN, HIFDE_RANK_PARAMS,
+    HIFDE_PROF_GROUP_DOWN, HIFDE_PROF_SWEEP_UP_ONE, HIFDE_PROF_CONTRIB_ADD,
+    HIFDE_PROF_CLASSES, HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN, HIFDE_RANK_PARAMS,
 )
 
 

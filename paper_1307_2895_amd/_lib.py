@@ -40,7 +40,8 @@ HIFDE_RANK_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP = 0, 1, 2, 3
 HIFDE_PROF_SWEEP_UP_WHOLE, HIFDE_PROF_SWEEP_DOWN_WHOLE = 4, 5
 HIFDE_PROF_GROUP_UP, HIFDE_PROF_GROUP_DOWN = 6, 7
-HIFDE_PROF_CLASSES = 8
+HIFDE_PROF_SWEEP_UP_ONE, HIFDE_PROF_CONTRIB_ADD = 8, 9
+HIFDE_PROF_CLASSES = 10
 
 
 class HifdeError(RuntimeError):

@@ -54,6 +54,7 @@ struct PackDev {
   int64_t dv;
   int64_t idx;
   int64_t t_off;     // skeleton fronts: interpolation matrix T (k x p, ld k)
+  int64_t cq;        // cells swept in one launch: first row of its x_q update
   int32_t s, p;
 };
 

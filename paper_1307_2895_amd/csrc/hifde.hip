@@ -1,5 +1,6 @@
 // HIF-DE on gfx950: C ABI, factorization driver (Algorithm 4.1), F^-1
 // application and preconditioned conjugate gradients.
+#include <functional>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -201,6 +202,14 @@ struct SweepSet {
   int2* down = nullptr;
   int2* upf[2] = {nullptr, nullptr};
   int2* downf = nullptr;
+  // upward step of both colors in one launch (cells of level 0): its items,
+  // and per distinct q unknown qunk[j] the contribution rows
+  // qsrc[qptr[j] .. qptr[j + 1]) that update it, color 0 first
+  std::vector<int2> upc_h;
+  std::vector<int32_t> qunk_h, qptr_h, qsrc_h;
+  int64_t cq_rows = 0;
+  int2* upc = nullptr;
+  int32_t *qunk = nullptr, *qptr = nullptr, *qsrc = nullptr;
 };
 
 // Work lists and per-color work of the fronts in S.ph (colors[i] per front).
@@ -254,12 +263,62 @@ static void sweep_layout(SweepSet& S, const std::vector<FrontDev>& fh, bool wors
   }
 }
 
-static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool colored) {
+// Rows of the contribution buffer for the one-launch upward step of
+// colored fronts: front f (with pivots) owns rows f.cq .. f.cq + s - p - 1,
+// and each distinct q unknown gets the rows that update it, color 0 first
+// (a counting sort by unknown; N unknowns).  Left empty when two fronts of
+// one color share a q unknown (the colored launches would race there).
+static void contrib_plan(SweepSet& S, const std::vector<int32_t>& idx_h,
+                         const std::vector<int>& colors, int64_t N) {
+  int64_t rows = 0;
+  std::vector<int32_t> start(size_t(N) + 1, 0);
+  for (PackDev& f : S.ph) {
+    if (f.p == 0) continue;
+    f.cq = rows;
+    rows += f.s - f.p;
+    for (int i = f.p; i < f.s; ++i) ++start[size_t(idx_h[size_t(f.idx) + i]) + 1];
+  }
+  if (rows == 0 || rows > INT32_MAX) return;
+  for (int64_t u = 0; u < N; ++u) start[size_t(u) + 1] += start[size_t(u)];
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  std::vector<int32_t> src(static_cast<size_t>(rows));
+  std::vector<int8_t> col(static_cast<size_t>(rows));
+  for (int c = 0; c < 2; ++c)
+    for (size_t fi = 0; fi < S.ph.size(); ++fi) {
+      const PackDev& f = S.ph[fi];
+      if (f.p == 0 || colors[fi] != c) continue;
+      for (int i = f.p; i < f.s; ++i) {
+        const int32_t k = fill[size_t(idx_h[size_t(f.idx) + i])]++;
+        src[size_t(k)] = int32_t(f.cq + i - f.p);
+        col[size_t(k)] = int8_t(c);
+      }
+    }
+  std::vector<int32_t> qunk, qptr{0};
+  for (int64_t u = 0; u < N; ++u) {
+    const int32_t a = start[size_t(u)], b = start[size_t(u) + 1];
+    if (a == b) continue;
+    for (int32_t k = a + 1; k < b; ++k)
+      if (col[size_t(k)] <= col[size_t(k) - 1]) return;
+    qunk.push_back(int32_t(u));
+    qptr.push_back(b);
+  }
+  for (size_t fi = 0; fi < S.ph.size(); ++fi)
+    if (S.ph[fi].p > 0) S.upc_h.push_back(make_int2(int(fi), 0));
+  S.qunk_h = std::move(qunk);
+  S.qptr_h = std::move(qptr);
+  S.qsrc_h = std::move(src);
+  S.cq_rows = rows;
+}
+
+// contrib_n > 0: also plan the one-launch upward step (contrib_n unknowns).
+static void build_sweep(SweepSet& S, const std::vector<FrontDev>& fh, bool colored,
+                        const std::vector<int32_t>* idx_h = nullptr, int64_t contrib_n = 0) {
   sweep_layout(S, fh, false);
   std::vector<int> colors(fh.size(), 0);
   if (colored)
     for (size_t i = 0; i < fh.size(); ++i) colors[i] = fh[i].color & 1;
   sweep_items(S, colors);
+  if (idx_h && contrib_n > 0) contrib_plan(S, *idx_h, colors, contrib_n);
 }
 
 static void upload_sweep(SweepSet& S, Arena& mem, hipStream_t st) {
@@ -270,6 +329,12 @@ static void upload_sweep(SweepSet& S, Arena& mem, hipStream_t st) {
   S.upf[0] = mem.upload(S.upf_h[0], st);
   S.upf[1] = mem.upload(S.upf_h[1], st);
   S.downf = mem.upload(S.downf_h, st);
+  if (!S.upc_h.empty()) {
+    S.upc = mem.upload(S.upc_h, st);
+    S.qunk = mem.upload(S.qunk_h, st);
+    S.qptr = mem.upload(S.qptr_h, st);
+    S.qsrc = mem.upload(S.qsrc_h, st);
+  }
 }
 
 // Device description of the cells of one level; depends on the plan only, so
@@ -383,8 +448,8 @@ struct hifde_factor_s {
   Arena mem;
   DevMem diag, offd;
   hifde_stats_t stats{};
-  // solver scratch
-  DevMem X, Z;
+  // solver scratch (C: x_q contributions of the one-launch upward step)
+  DevMem X, Z, C;
   DevMem pcg;
   int64_t pcg_rhs = 0;
   // kernel timing (hifde_profile)
@@ -419,7 +484,7 @@ struct hifde_factor_s {
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_nrhs = 0;
-  const void *g_x = nullptr, *g_z = nullptr;
+  const void *g_x = nullptr, *g_z = nullptr, *g_c = nullptr;
   // The side stream, after the work queued on st so far.
   hipStream_t side_after(hipStream_t st) {
     if (!side) HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -427,6 +492,16 @@ struct hifde_factor_s {
     HIP_CHECK(hipEventRecord(e, st));
     HIP_CHECK(hipStreamWaitEvent(side, e, 0));
     return side;
+  }
+  // Apply form and packing of the last cell level: queued on the side
+  // stream once that level's IDs are launched, so that they do not compete
+  // with the IDs, whose ranks the host waits for.
+  std::function<void(hipStream_t)> side_work;
+  void flush_side(hipStream_t st) {
+    if (!side_work) return;
+    std::function<void(hipStream_t)> w = std::move(side_work);
+    side_work = nullptr;
+    w(side_after(st));
   }
   // Later work on st waits for the side stream's.
   void join_side(hipStream_t st) {
@@ -538,7 +613,9 @@ static void append_trips(std::vector<TripDev>& out, const std::vector<Trip>& in)
   for (const Trip& t : in) out.push_back({t.i, t.j, t.ref});
 }
 
-static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, const LevelPlan& lp) {
+// `one_launch`: also plan the upward step of both colors in one launch.
+static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, const LevelPlan& lp,
+                                                    bool one_launch) {
   auto cs = std::make_shared<CellStatic>();
   int64_t off = 0;
   for (const Cell& c : lp.cells) {
@@ -564,7 +641,7 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
   cs->elems = off;
   cs->ncell = int(cs->fh.size());
   cs->maps_h = &lp.maps;
-  build_sweep(cs->sw, cs->fh, true);
+  build_sweep(cs->sw, cs->fh, true, &cs->idx_h, one_launch ? F.g.N : 0);
   return cs;
 }
 
@@ -854,6 +931,7 @@ static std::vector<FrontDev> sorted_by_p(const std::vector<FrontDev>& fh) {
 
 template <typename T, typename TS>
 static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
+  F.flush_side(st);
   Planner& P = *F.planner;
   CellLevel& D = F.cl[l];
   PhaseTimer tm;
@@ -862,7 +940,7 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   } else {
     if (l > 0) P.plan_cells(l);
     tm.mark("  plan cells", l);
-    D.st = make_cell_static(F, *P.level(l).plan);
+    D.st = make_cell_static(F, *P.level(l).plan, l == 0);
     tm.mark("  cell descriptors", l);
     if (l == 0) {
       tree->c0 = D.st;
@@ -914,17 +992,19 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
       });
   batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, var);
   // The apply form and its packed copy are read by the sweeps only: they run
-  // on the side stream, beside this level's IDs and the next level's
-  // planning.  They touch the first p columns of each front; the groups and
-  // later levels read the update blocks.
-  hipStream_t ss = F.side_after(st);
-  const int ivar = tune_choice(
-      F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 2, 1, D.pool,
-      size_t(S.elems) * sizeof(T), ss,
-      [&](int v) { apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v); });
-  apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar);
-  pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
-                 &D.dinv, ss);
+  // on the side stream after this level's IDs, beside the host's skeleton
+  // bookkeeping and the next level's planning.  They touch the first p
+  // columns of each front; the groups and later levels read the update
+  // blocks.
+  F.side_work = [&F, &D, &S, fs = std::move(fs), fs_d](hipStream_t ss) {
+    const int ivar = tune_choice(
+        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 2, 1, D.pool,
+        size_t(S.elems) * sizeof(T), ss,
+        [&](int v) { apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v); });
+    apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar);
+    pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
+                   &D.dinv, ss);
+  };
 }
 
 // The input flags of k_stencil (read once, at the first synchronization).
@@ -1061,6 +1141,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     HIP_CHECK(hipGetLastError());
   }
   if (!skel || G.ngroup == 0) {
+    F.flush_side(st);
     for (int gi = 0; gi < G.ngroup; ++gi) P.set_skeleton(l, gi, G.gh[gi].nc, nullptr);
     P.finish_groups(l);
     G.nskel = 0;
@@ -1256,6 +1337,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     launch_fronts(pbound);
   }
 
+  F.flush_side(st);   // after the IDs
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
   HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
@@ -1271,11 +1353,12 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   G.ncskel = 0;
   G.tel = G.rrows = G.krows = 0;
   int rmax = 0;
+  for (int gi = 0; gi < G.ngroup; ++gi)
+    if (kh[gi] < 0 || kh[gi] > G.gh[gi].nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
+  P.set_skeletons(l, kh.data(), ph.data(), size_t(ncmax));
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];
-    if (k < 0 || k > d.nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
-    P.set_skeleton(l, gi, k, ph.data() + size_t(gi) * ncmax);
     if (pre) {
       F.rank_groups += 1;
       F.rank_abs_err += std::abs(double(khat[gi]) - double(k));
@@ -1400,6 +1483,7 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
     tm.mark("groups", l);
   }
   cells_level<double, T>(F, tree, L, st);
+  F.flush_side(st);
   tm.mark("top", L);
   if (F.plan_only) return;
   check_input(F, st);
@@ -1645,6 +1729,57 @@ static bool sweep_up(hifde_factor_s& F, int cls, int level, const SweepSet& S, i
   return true;
 }
 
+// The upward step of both colors of a cell level in one launch
+// (k_sweep_up_c) and the addition of the x_q contributions
+// (k_contrib_add).  Returns false when the level has no contribution plan
+// or the whole-front form does not apply; the caller then launches the two
+// colors.
+template <typename T, typename TX>
+static bool sweep_up_one(hifde_factor_s& F, int level, const SweepSet& S, const void* pk,
+                         const void* dinv, const int32_t* idx, TX* X, TX* Z, int nrhs,
+                         hipStream_t st) {
+  if (S.upc_h.empty() || F.row_tiles) return false;
+  const int nf = int(S.upc_h.size()), nq = int(S.qunk_h.size());
+  if (int64_t(nq) * nrhs >= INT32_MAX) return false;
+  SweepShape g{};
+  if (!sweep_whole<T>(nf, nrhs, S.kpf, &g)) return false;
+  if (F.C.bytes < size_t(S.cq_rows) * size_t(nrhs) * sizeof(T))
+    throw Error(HIFDE_ESTATE, "contribution buffer too small");
+  T* C = F.C.as<T>();
+  const size_t esz = sizeof(T), xsz = sizeof(TX);
+  Work w{0, 0};
+  if (F.prof_mask) {
+    const double fac = S.fac[0] + S.fac[1], pr = S.prows[0] + S.prows[1];
+    const double qr = double(S.cq_rows);
+    w = {fac * esz + pr * 4 + (2 * pr * xsz + qr * esz) * nrhs, 2.0 * nrhs * fac};
+  }
+  const T* P = static_cast<const T*>(pk);
+  const T* Dv = static_cast<const T*>(dinv);
+  const bool vec = nrhs % int(16 / sizeof(TX)) == 0;
+  timed(F, HIFDE_PROF_SWEEP_UP_ONE, level, w.bytes, w.flops, st, [&] {
+#define HIFDE_UPC(NTV, VV)                                                                   \
+  hipLaunchKernelGGL((k_sweep_up_c<T, TX, NTV, VV>), dim3(g.grid), dim3(kThreads), g.lds, st, \
+                     S.packs, S.upc, nf, g.nch, P, Dv, idx, X, Z, C, nrhs)
+    if (vec) {
+      if (g.NT == 1) HIFDE_UPC(1, true); else if (g.NT == 2) HIFDE_UPC(2, true); else HIFDE_UPC(4, true);
+    } else {
+      if (g.NT == 1) HIFDE_UPC(1, false); else if (g.NT == 2) HIFDE_UPC(2, false); else HIFDE_UPC(4, false);
+    }
+#undef HIFDE_UPC
+  });
+  const double nc = double(S.qsrc_h.size());
+  const Work wa = F.prof_mask ? Work{double(nq) * nrhs * 2 * xsz + nc * nrhs * esz +
+                                         double(nq) * 8 + nc * 4,
+                                     double(nc) * nrhs}
+                              : Work{0, 0};
+  const unsigned blocks = unsigned((int64_t(nq) * nrhs + kThreads - 1) / kThreads);
+  timed(F, HIFDE_PROF_CONTRIB_ADD, level, wa.bytes, wa.flops, st, [&] {
+    hipLaunchKernelGGL((k_contrib_add<T, TX>), dim3(blocks), dim3(kThreads), 0, st, S.qunk,
+                       S.qptr, S.qsrc, nq, static_cast<const T*>(C), X, nrhs);
+  });
+  return true;
+}
+
 // One downward sweep launch; `tpool` as in sweep_up (the interpolation
 // follows the step, in the same launch).
 template <typename T, typename TX>
@@ -1699,8 +1834,10 @@ static void apply_inverse(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream_t
   for (int l = 0; l < L; ++l) {
     CellLevel& C = F.cl[l];
     const CellStatic& S = *C.st;
-    for (int color = 0; color < 2; ++color)
-      sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, S.sw, color, C.pk, C.dinv, S.idx, X, Z, nrhs, st);
+    if (!sweep_up_one<T, TX>(F, l, S.sw, C.pk, C.dinv, S.idx, X, Z, nrhs, st))
+      for (int color = 0; color < 2; ++color)
+        sweep_up<T, TX>(F, HIFDE_PROF_SWEEP_UP, l, S.sw, color, C.pk, C.dinv, S.idx, X, Z, nrhs,
+                        st);
     GroupLevel& G = F.gl[l];
     if (G.nskel > 0) {
       // interpolation and elimination of ř in one launch when the fronts fit
@@ -1751,7 +1888,7 @@ static void apply_inverse_g(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream
     apply_inverse<T, TX>(F, X, Z, nrhs, st);
     return;
   }
-  if (!(F.gexec && F.g_nrhs == nrhs && F.g_x == X && F.g_z == Z)) {
+  if (!(F.gexec && F.g_nrhs == nrhs && F.g_x == X && F.g_z == Z && F.g_c == F.C.p)) {
     if (F.gexec) {
       HIP_CHECK(hipGraphExecDestroy(F.gexec));
       F.gexec = nullptr;
@@ -1776,6 +1913,7 @@ static void apply_inverse_g(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream
     F.g_nrhs = nrhs;
     F.g_x = X;
     F.g_z = Z;
+    F.g_c = F.C.p;
   }
   HIP_CHECK(hipGraphLaunch(F.gexec, st));
 }
@@ -1784,6 +1922,9 @@ static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
   const size_t need = size_t(F.g.N) * size_t(nrhs) * 8;
   if (F.X.bytes < need) F.X.alloc(need);
   if (F.Z.bytes < need) F.Z.alloc(need);
+  const int64_t rows = F.cl.empty() || !F.cl[0].st ? 0 : F.cl[0].st->sw.cq_rows;
+  const size_t cneed = size_t(rows) * size_t(nrhs) * 8;
+  if (cneed > 0 && F.C.bytes < cneed) F.C.alloc(cneed);
 }
 
 
@@ -2103,13 +2244,19 @@ int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level, hifde_f
       P.plan_groups(l);
       tm.mark("plan groups", l);
       const auto& groups = P.level(l).groups();
+      size_t stride = 1;
+      for (const auto& G : groups) stride = std::max(stride, G.c.size());
+      std::vector<int32_t> ks(groups.size()), pos(groups.size() * stride);
       for (size_t gi = 0; gi < groups.size(); ++gi) {
-        std::vector<int32_t> sk;
-        for (int32_t i = 0; i < int32_t(groups[gi].c.size()); ++i)
-          if (redundant_level[groups[gi].c[i]] != 2 * l + 1) sk.push_back(i);
-        P.set_skeleton(l, int(gi), int(sk.size()), sk.data());
+        // skeleton positions listed in decreasing order (set_skeletons sorts)
+        int k = 0;
+        for (int32_t i = int32_t(groups[gi].c.size()) - 1; i >= 0; --i)
+          if (redundant_level[groups[gi].c[i]] != 2 * l + 1) pos[gi * stride + size_t(k++)] = i;
+        ks[gi] = k;
       }
+      P.set_skeletons(l, ks.data(), pos.data(), stride);
       P.finish_groups(l);
+      tm.mark("skeletons", l);
     }
     P.plan_cells(F->g.L);
     F->prec = HIFDE_FP64;

@@ -796,13 +796,52 @@ void Planner::set_skeleton(int l, int gi, int k, const int32_t* sk_pos) {
   for (int32_t i = 0; i < nc; ++i) (is_sk[i] ? R.sk : R.rd).push_back(G.c[i]);
 }
 
+void Planner::set_skeletons(int l, const int32_t* ks, const int32_t* pos, size_t stride) {
+  Level& lev = lv_[l];
+  const std::vector<Group>& groups = lev.plan->groups;
+  parallel_for(groups.size(), 32, workers_, [&](size_t gi, int) {
+    const Group& G = groups[gi];
+    GroupRes& R = lev.res.at(gi);
+    const int32_t nc = int32_t(G.c.size());
+    const int k = ks[gi];
+    R.sk.clear();
+    R.rd.clear();
+    if (k >= nc) {
+      R.skel = false;
+      R.k = nc;
+      return;
+    }
+    if (k < 0) throw std::runtime_error("negative rank");
+    R.skel = true;
+    R.k = k;
+    // skeleton positions in increasing order, then both lists in the order
+    // of c (as set_skeleton makes them)
+    std::vector<int32_t>& sp = R.sk;
+    sp.assign(pos + gi * stride, pos + gi * stride + k);
+    std::sort(sp.begin(), sp.end());
+    for (int i = 0; i < k; ++i)
+      if (sp[i] < 0 || sp[i] >= nc || (i > 0 && sp[i] == sp[i - 1]))
+        throw std::runtime_error("invalid skeleton position");
+    R.rd.reserve(size_t(nc - k));
+    int j = 0;
+    for (int32_t i = 0; i < nc; ++i) {
+      if (j < k && sp[j] == i) {
+        sp[j++] = G.c[i];
+      } else {
+        R.rd.push_back(G.c[i]);
+      }
+    }
+  });
+}
+
 void Planner::finish_groups(int l) {
   const Level& lev = lv_[l];
-  for (size_t gi = 0; gi < lev.groups().size(); ++gi) {
+  // groups are disjoint: each byte is written by one group
+  parallel_for(lev.groups().size(), 64, workers_, [&](size_t gi, int) {
     for (int32_t d : lev.groups()[gi].c) grouped_[d] = 1;
     if (lev.res[gi].skel)
       for (int32_t d : lev.res[gi].rd) active_[d] = 0;
-  }
+  });
   drop_inactive();
 }
 

@@ -128,6 +128,9 @@ class Planner {
   // Record the skeleton choice of group gi of level l+1/2: k skeletons at
   // the given positions of c (sorted ascending).  k >= |c| leaves it alone.
   void set_skeleton(int l, int gi, int k, const int32_t* sk_pos);
+  // set_skeleton of every group of level l at once (threaded): group gi has
+  // rank ks[gi] and skeleton positions pos[gi * stride ..]
+  void set_skeletons(int l, const int32_t* ks, const int32_t* pos, size_t stride);
   // Finish level l+1/2 after every set_skeleton call.
   void finish_groups(int l);
 
