@@ -29,12 +29,12 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
-# The kernel the roofline object describes: the whole-front upward sweep of
-# F^-1 over cells (every launch of k_sweep_up_f<float, float, 1, true,
-# false>, the 16-right-hand-side instance: both colors of the levels with
-# many cells), the kernel with the most time per step.  Its launches are
-# exactly those of the profile class HIFDE_PROF_SWEEP_UP_WHOLE.
-DOMINANT_KERNEL = "k_sweep_up_f<float, float, 1, true, false>"
+# The kernel the roofline object describes: the upward sweep of F^-1 over
+# the level-0 cells, both colors in one launch (k_sweep_up_c<float, float,
+# 1, true>, the 16-right-hand-side instance), the kernel with the most time
+# per step.  Its launches are exactly those of the profile class
+# HIFDE_PROF_SWEEP_UP_ONE.
+DOMINANT_KERNEL = "k_sweep_up_c<float, float, 1, true>"
 DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
 CALIB_COPY_BYTES = 512 << 20
 
@@ -216,12 +216,12 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if profile:
-            H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP_WHOLE, -1)
+            H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP_ONE, -1)
         u, its, rel = H.hifde_pcg(F, f_d, tol=1e-12, maxit=200)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if profile:
-            r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP_WHOLE)
+            r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP_ONE)
             for k in prof:
                 prof[k] += r[k]
         st = H.hifde_stats(F)
