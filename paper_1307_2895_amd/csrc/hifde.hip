@@ -712,6 +712,13 @@ static void upload_group_static(GroupStatic& gs, Arena& mem, hipStream_t st) {
   gs.on_device = true;
 }
 
+// Grid of a front_tile launch: nf fronts, nt tiles each.
+static unsigned front_tile_grid(unsigned nf, int64_t nt, const char* what) {
+  const int64_t g = int64_t(8) * ((nf + 7) / 8) * nt;
+  if (g > INT32_MAX) throw Error(HIFDE_EINVAL, std::string("front too large for the ") + what);
+  return unsigned(g);
+}
+
 // Batched partial LDL^T of a set of fronts already in `pool`.
 // Fronts with more than j pivots: all of them, or (fh sorted by p,
 // descending) the leading ones only.
@@ -759,13 +766,13 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
                          fronts_d, j0);
     }
     if (maxt > 0) {
-      if (maxt > 65535) throw Error(HIFDE_EINVAL, "front too large for the trailing-update grid");
+      const unsigned g = front_tile_grid(nf, maxt, "trailing-update grid");
       if (variant == LDL_MFMA)
-        hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(nf, unsigned(maxt)), dim3(kThreads), 0, st,
-                           pool, fronts_d, j0);
+        hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d,
+                           j0, int(nf), int(maxt));
       else
-        hipLaunchKernelGGL(k_ldl_update<T>, dim3(nf, unsigned(maxt)), dim3(kThreads), 0, st, pool,
-                           fronts_d, j0);
+        hipLaunchKernelGGL(k_ldl_update<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, j0,
+                           int(nf), int(maxt));
     }
   }
   HIP_CHECK(hipGetLastError());
@@ -796,13 +803,13 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
     const unsigned na = active_fronts(fh, J, sorted);
     if (na == 0) continue;
     if (tiles > 0) {
-      if (tiles > 65535) throw Error(HIFDE_EINVAL, "front too large for the inversion grid");
+      const unsigned g = front_tile_grid(na, tiles, "inversion grid");
       if (variant == 1)
-        hipLaunchKernelGGL(k_inv_step_mfma<T>, dim3(na, unsigned(tiles)), dim3(kThreads), 0, st,
-                           pool, fronts_d, J, tmp, toff_d);
+        hipLaunchKernelGGL(k_inv_step_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, J,
+                           tmp, toff_d, int(na), int(tiles));
       else
-        hipLaunchKernelGGL(k_inv_step<T>, dim3(na, unsigned(tiles)), dim3(kThreads), 0, st, pool,
-                           fronts_d, J, tmp, toff_d);
+        hipLaunchKernelGGL(k_inv_step<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
+                           toff_d, int(na), int(tiles));
     }
     hipLaunchKernelGGL(k_inv_commit<T>, dim3(na), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
                        toff_d);
