@@ -1345,12 +1345,13 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   }
 
   F.flush_side(st);   // after the IDs
+  tm.mark("  launch IDs", l);
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
+  // (copies to pageable memory return once the IDs are done)
   HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
-  PhaseTimer tw;
   HIP_CHECK(hipStreamSynchronize(st));
-  tw.mark("  wait for IDs", l);
+  tm.mark("  wait for IDs", l);
   check_input(F, st);
   // record skeletons; build the skeleton fronts
   int64_t fg_off = 0;
@@ -1363,6 +1364,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   for (int gi = 0; gi < G.ngroup; ++gi)
     if (kh[gi] < 0 || kh[gi] > G.gh[gi].nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
   P.set_skeletons(l, kh.data(), ph.data(), size_t(ncmax));
+  tm.mark("  set skeletons", l);
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];
@@ -1392,8 +1394,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     G.gsel_h.push_back(gi);
     G.ncskel = std::max(G.ncskel, int(d.nc));
   }
+  tm.mark("  skeleton lists", l);
   P.finish_groups(l);
-  tm.mark("  skeletons", l);
+  tm.mark("  finish groups", l);
   G.nskel = int(G.gsel_h.size());
   G.groups = F.mem.upload(G.gh, st);
   if (pre) {
@@ -1459,6 +1462,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   upload_sweep(G.sw, F.mem, st);
   pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.pt,
                  &G.dinv, st);
+  tm.mark("  skeleton fronts", l);
 }
 
 template <typename T>
@@ -1935,6 +1939,19 @@ static void ensure_X(hifde_factor_s& F, int64_t nrhs) {
 }
 
 
+// Blocks of a PCG pass: one full round of the device at the kernel's
+// occupancy (its register count decides how many work-groups a CU holds;
+// a second, partial round would leave most of the device idle), a multiple
+// of 8 for the XCD-major block ranges, at most kPcgBlocks.
+static unsigned pcg_blocks(const void* kernel) {
+  int per_cu = 0, dev = 0, cus = 0;
+  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0));
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t nb = (int64_t(std::max(per_cu, 1)) * std::max(cus, 1)) / 8 * 8;
+  return unsigned(std::min<int64_t>(std::max<int64_t>(nb, 8), kPcgBlocks));
+}
+
 // Conjugate gradients preconditioned by F^-1 (Section 5), one independent
 // iteration per column, all vectors unknown-major in double; TR is the type
 // of the preconditioner's vectors (float: flexible beta).  Returns whether
@@ -1971,6 +1988,9 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   double* d1 = sc + 3 * nr;
   int* live = reinterpret_cast<int*>(sc + 8 * nr);
   const unsigned nb = kPcgBlocks;
+  const unsigned nb_ap = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_ap<TR, W, DIM>));
+  const unsigned nb_xr = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_xr<TR, W, DIM>));
+  const unsigned nb_rz = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_rz<TR, W>));
   const int dim = F.g.dim;
   const int64_t side = F.g.n;
   const DivN dn = make_divn(uint32_t(side));
@@ -1984,9 +2004,9 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   HIP_CHECK(hipMemsetAsync(alpha, 0, size_t(nr) * 8, st));
   HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
   // ||f||^2 and the preconditioner's copy of r (alpha = 0: x, r unchanged)
-  hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb), dim3(kThreads), 0, st, N, nr, dn, diag,
+  hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb_xr), dim3(kThreads), 0, st, N, nr, dn, diag,
                      offd, alpha, pa, x, r, rc, 0, px);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_xr), nr, 0, px, d1);
   std::vector<int> liveh(nr, 1), itsh(nr, 0);
   std::vector<double> fh(nr), h1(nr);
   HIP_CHECK(hipMemcpyAsync(fh.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
@@ -1998,22 +2018,22 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
   apply_inverse_g<TP, TR>(F, rc, Zs, nr, st);
   // rz = r.z, beta = 0 (rz was 0)
-  hipLaunchKernelGGL((k_pcg_rz<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, pz);
-  hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, px, 0, rz,
-                     live, beta);
+  hipLaunchKernelGGL((k_pcg_rz<TR, W>), dim3(nb_rz), dim3(kThreads), 0, st, N, nr, rc, r, pz);
+  hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb_rz), int(nb_xr), nr,
+                     pz, px, 0, rz, live, beta);
   int it = 0;
   while (it < maxit) {
     bool any = false;
     for (int c = 0; c < nr; ++c) any = any || liveh[c];
     if (!any) break;
     ++it;
-    hipLaunchKernelGGL((k_pcg_ap<TR, W, DIM>), dim3(nb), dim3(kThreads), 0, st, N, nr, dn, diag,
-                       offd, beta, rc, pa, pb, pz);
-    hipLaunchKernelGGL(k_reduce_alpha, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, rz, live,
-                       alpha);
-    hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb), dim3(kThreads), 0, st, N, nr, dn, diag,
-                       offd, alpha, pb, x, r, rc, flexible, px);
-    hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
+    hipLaunchKernelGGL((k_pcg_ap<TR, W, DIM>), dim3(nb_ap), dim3(kThreads), 0, st, N, nr, dn,
+                       diag, offd, beta, rc, pa, pb, pz);
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(nr), dim3(kThreads), 0, st, int(nb_ap), nr, pz, rz,
+                       live, alpha);
+    hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb_xr), dim3(kThreads), 0, st, N, nr, dn,
+                       diag, offd, alpha, pb, x, r, rc, flexible, px);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_xr), nr, 0, px, d1);
     std::swap(pa, pb);
     HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
@@ -2030,9 +2050,9 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
     if (changed) HIP_CHECK(hipMemcpyAsync(live, liveh.data(), nr * 4, hipMemcpyHostToDevice, st));
     if (!anyl || it == maxit) break;
     apply_inverse_g<TP, TR>(F, rc, Zs, nr, st);
-    hipLaunchKernelGGL((k_pcg_rz<TR, W>), dim3(nb), dim3(kThreads), 0, st, N, nr, rc, r, pz);
-    hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, pz, px,
-                       flexible, rz, live, beta);
+    hipLaunchKernelGGL((k_pcg_rz<TR, W>), dim3(nb_rz), dim3(kThreads), 0, st, N, nr, rc, r, pz);
+    hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb_rz), int(nb_xr), nr,
+                       pz, px, flexible, rz, live, beta);
   }
   // true residuals ||f - A x|| (A x into pb, f into r)
   hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, dim, side, diag, offd,
