@@ -94,11 +94,17 @@ struct MemPool {
       }
     }
     void* p = nullptr;
+    static const bool timing = getenv("HIFDE_TIMING") != nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
     if (hipMalloc(&p, b) != hipSuccess) {
       (void)hipGetLastError();
       trim();
       HIP_CHECK(hipMalloc(&p, b));
     }
+    if (timing)
+      fprintf(stderr, "[hifde] pool miss: hipMalloc %zu bytes %.3f ms\n", b,
+              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                  .count());
     *cap = b;
     return p;
   }
@@ -110,6 +116,47 @@ struct MemPool {
     std::lock_guard<std::mutex> g(mu);
     for (auto& kv : kept) (void)hipFree(kv.second);
     kept.clear();
+  }
+};
+
+// Streams of freed factorizations, kept for later ones on the same device.
+// The first work on a newly created stream has taken milliseconds (its
+// binding to a hardware queue), so factorizations take bound streams from
+// here and give them back instead of creating and destroying their own.
+// They live as long as the process; all have the default priority.
+struct StreamCache {
+  std::mutex mu;
+  std::vector<std::pair<int, hipStream_t>> kept;   // (device, stream)
+  static StreamCache& get() {
+    static StreamCache* c = new StreamCache;       // never destroyed
+    return *c;
+  }
+  hipStream_t take() {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> g(mu);
+      for (size_t i = 0; i < kept.size(); ++i)
+        if (kept[i].first == dev) {
+          hipStream_t s = kept[i].second;
+          kept.erase(kept.begin() + std::ptrdiff_t(i));
+          return s;
+        }
+    }
+    hipStream_t s = nullptr;
+    HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  void give(hipStream_t s) {
+    if (!s) return;
+    hipDevice_t dev = 0;
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamDestroy(s);
+      return;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    kept.emplace_back(int(dev), s);
   }
 };
 
@@ -487,7 +534,7 @@ struct hifde_factor_s {
   const void *g_x = nullptr, *g_z = nullptr, *g_c = nullptr;
   // The side stream, after the work queued on st so far.
   hipStream_t side_after(hipStream_t st) {
-    if (!side) HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (!side) side = StreamCache::get().take();
     hipEvent_t e = new_event();
     HIP_CHECK(hipEventRecord(e, st));
     HIP_CHECK(hipStreamWaitEvent(side, e, 0));
@@ -527,13 +574,13 @@ struct hifde_factor_s {
     if (pool) (void)hipDeviceSynchronize();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
-    if (aux) (void)hipStreamDestroy(aux);
+    StreamCache::get().give(aux);
     aux = nullptr;
-    if (side) (void)hipStreamDestroy(side);
+    StreamCache::get().give(side);
     side = nullptr;
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
-    if (cap) (void)hipStreamDestroy(cap);
+    StreamCache::get().give(cap);
     cap = nullptr;
     for (ProfEvent& e : prof_ev) {
       if (e.a) (void)hipEventDestroy(e.a);
@@ -778,21 +825,40 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
   HIP_CHECK(hipGetLastError());
 }
 
+// Buffers of apply_form: the column block of B in flight, s x kNB per front,
+// and each front's offset in it.
 template <typename T>
-static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
-                       const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
-                       bool sorted = false, int variant = 1) {
-  if (fh.empty()) return;
+struct InvWork {
+  T* tmp = nullptr;
+  const int64_t* toff = nullptr;
+};
+template <typename T>
+static InvWork<T> apply_form_work(Arena& mem, const std::vector<FrontDev>& fh, hipStream_t st) {
   std::vector<int64_t> toff(fh.size());
   int64_t tot = 0;
-  int pmax = 0;
   for (size_t i = 0; i < fh.size(); ++i) {
     toff[i] = tot;
     tot += int64_t(fh[i].s) * kNB;
-    pmax = std::max(pmax, fh[i].p);
   }
-  T* tmp = mem.get<T>(size_t(std::max<int64_t>(tot, 1)));
-  const int64_t* toff_d = mem.upload(toff, st);
+  InvWork<T> w;
+  w.tmp = mem.get<T>(size_t(std::max<int64_t>(tot, 1)));
+  w.toff = mem.upload(toff, st);
+  return w;
+}
+
+// With `work` prepared beforehand (apply_form_work on another stream),
+// nothing is copied from the host here: a stream held behind an event can
+// make a pageable host copy wait for that event.
+template <typename T>
+static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
+                       const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
+                       bool sorted = false, int variant = 1, const InvWork<T>* work = nullptr) {
+  if (fh.empty()) return;
+  int pmax = 0;
+  for (const FrontDev& f : fh) pmax = std::max(pmax, f.p);
+  const InvWork<T> w = work ? *work : apply_form_work<T>(mem, fh, st);
+  T* tmp = w.tmp;
+  const int64_t* toff_d = w.toff;
   for (int J = ((pmax - 1) / kNB) * kNB; J >= 0 && pmax > 0; J -= kNB) {
     int64_t tiles = 0;
     for (const auto& f : fh) {
@@ -990,8 +1056,11 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   }
   HIP_CHECK(hipGetLastError());
   // elimination and apply form in buckets of pivot count (sorted fronts)
-  const std::vector<FrontDev> fs = sorted_by_p(S.fh);
+  std::vector<FrontDev> fs = sorted_by_p(S.fh);
   const FrontDev* fs_d = F.mem.upload(fs, st);
+  // the apply form's buffers (uploaded here, before the elimination is
+  // queued: see apply_form)
+  const InvWork<T> iw = apply_form_work<T>(F.mem, fs, st);
   const int var = tune_choice(
       F, tune_key(FAM_LDL, int(sizeof(T)), S.pmax, S.smax, S.ncell), LDL_VARIANTS, LDL_MFMA, D.pool,
       size_t(S.elems) * sizeof(T), st, [&](int v) {
@@ -1003,12 +1072,13 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   // bookkeeping and the next level's planning.  They touch the first p
   // columns of each front; the groups and later levels read the update
   // blocks.
-  F.side_work = [&F, &D, &S, fs = std::move(fs), fs_d](hipStream_t ss) {
+  F.side_work = [&F, &D, &S, fs = std::move(fs), fs_d, iw](hipStream_t ss) {
     const int ivar = tune_choice(
         F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 2, 1, D.pool,
-        size_t(S.elems) * sizeof(T), ss,
-        [&](int v) { apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v); });
-    apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar);
+        size_t(S.elems) * sizeof(T), ss, [&](int v) {
+          apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v, &iw);
+        });
+    apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar, &iw);
     pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
                    &D.dinv, ss);
   };
@@ -1072,7 +1142,7 @@ static void predict_ranks(hifde_factor_s& F, GroupLevel& G, int l) {
   const int ng = G.ngroup;
   if (ng == 0) return;
   if (!F.aux) {
-    HIP_CHECK(hipStreamCreateWithFlags(&F.aux, hipStreamNonBlocking));
+    F.aux = StreamCache::get().take();
   }
   HIP_CHECK(hipStreamWaitEvent(F.aux, F.offd_ev, 0));
   float* feat = F.mem.get<float>(size_t(ng) * kRankF);
@@ -1147,6 +1217,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                        F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_prev);
     HIP_CHECK(hipGetLastError());
   }
+  tm.mark("  group bases", l);
   if (!skel || G.ngroup == 0) {
     F.flush_side(st);
     for (int gi = 0; gi < G.ngroup; ++gi) P.set_skeleton(l, gi, G.gh[gi].nc, nullptr);
@@ -1195,6 +1266,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                        S.maps, S.gtrips, F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_cur);
   }
   HIP_CHECK(hipGetLastError());
+  tm.mark("  gather", l);
   G.perm_stride = ncmax;
   G.kout = F.mem.get<int32_t>(G.ngroup);
   G.perm = F.mem.get<int32_t>(size_t(G.ngroup) * ncmax);
@@ -1344,8 +1416,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     launch_fronts(pbound);
   }
 
-  F.flush_side(st);   // after the IDs
   tm.mark("  launch IDs", l);
+  F.flush_side(st);   // after the IDs
+  tm.mark("  side work", l);
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
   // (copies to pageable memory return once the IDs are done)
   HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
@@ -1904,7 +1977,7 @@ static void apply_inverse_g(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream
       HIP_CHECK(hipGraphExecDestroy(F.gexec));
       F.gexec = nullptr;
     }
-    if (!F.cap) HIP_CHECK(hipStreamCreateWithFlags(&F.cap, hipStreamNonBlocking));
+    if (!F.cap) F.cap = StreamCache::get().take();
     HIP_CHECK(hipStreamBeginCapture(F.cap, hipStreamCaptureModeThreadLocal));
     hipGraph_t g = nullptr;
     try {
