@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -205,6 +206,10 @@ struct PinnedMem {
 
 // Bump allocator for the device buffers of one factorization: a few large
 // hipMalloc calls instead of one per array, all released together.
+// Host-to-device uploads through arenas: count, bytes and host time spent
+// in the copy calls (printed per factorization under HIFDE_TIMING).
+static std::atomic<int64_t> g_up_n{0}, g_up_bytes{0}, g_up_ns{0};
+
 struct Arena {
   std::vector<DevMem> chunks;
   size_t used = 0;
@@ -227,8 +232,14 @@ struct Arena {
   template <class T> T* get(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
   template <class T> T* upload(const std::vector<T>& v, hipStream_t st) {
     T* d = get<T>(std::max<size_t>(1, v.size()));
-    if (!v.empty())
+    if (!v.empty()) {
+      const auto t0 = std::chrono::steady_clock::now();
       HIP_CHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+      g_up_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(
+                     std::chrono::steady_clock::now() - t0).count();
+      g_up_n += 1;
+      g_up_bytes += int64_t(v.size() * sizeof(T));
+    }
     return d;
   }
 };
@@ -1569,6 +1580,11 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   cells_level<double, T>(F, tree, L, st);
   F.flush_side(st);
   tm.mark("top", L);
+  if (tm.on) {
+    fprintf(stderr, "[hifde] uploads: %lld, %.1f KB, %.3f ms in the copy calls\n",
+            static_cast<long long>(g_up_n.exchange(0)), double(g_up_bytes.exchange(0)) / 1024,
+            double(g_up_ns.exchange(0)) * 1e-6);
+  }
   if (F.plan_only) return;
   check_input(F, st);
   // pivot checks of every level at once (one synchronization)
