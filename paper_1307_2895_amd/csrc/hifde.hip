@@ -818,11 +818,9 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     // bound, so many small work-groups per CU do better than few large ones
     hipLaunchKernelGGL(k_ldl_diag<T>, dim3(nf), dim3(kDiagThreads), 0, st, pool, fronts_d, j0,
                        info_d);
-    if (maxr > 0) {
-      if (maxr > 65535) throw Error(HIFDE_EINVAL, "front too large for the panel grid");
-      hipLaunchKernelGGL(k_ldl_rows<T>, dim3(nf, unsigned(maxr)), dim3(kThreads), 0, st, pool,
-                         fronts_d, j0);
-    }
+    if (maxr > 0)
+      hipLaunchKernelGGL(k_ldl_rows<T>, dim3(front_tile_grid(nf, maxr, "panel grid")),
+                         dim3(kThreads), 0, st, pool, fronts_d, j0, int(nf), int(maxr));
     if (maxt > 0) {
       const unsigned g = front_tile_grid(nf, maxt, "trailing-update grid");
       if (variant == LDL_MFMA)
@@ -1449,6 +1447,17 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     if (kh[gi] < 0 || kh[gi] > G.gh[gi].nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
   P.set_skeletons(l, kh.data(), ph.data(), size_t(ncmax));
   tm.mark("  set skeletons", l);
+  {
+    size_t nidx = 0, nsk = 0;
+    for (int gi = 0; gi < G.ngroup; ++gi)
+      if (kh[gi] < G.gh[gi].nc) {
+        nidx += size_t(G.gh[gi].nc);
+        nsk += 1;
+      }
+    G.idx_h.reserve(nidx);
+    G.ff.reserve(nsk);
+    G.gsel_h.reserve(nsk);
+  }
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];

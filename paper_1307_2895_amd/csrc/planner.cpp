@@ -411,10 +411,32 @@ int32_t* Planner::loc(int w) {
 }
 
 void Planner::drop_inactive() {
-  size_t w = 0;
-  for (size_t i = 0; i < act_.size(); ++i)
-    if (active_[act_[i]]) act_[w++] = act_[i];
-  act_.resize(w);
+  const size_t n = act_.size();
+  constexpr size_t kBlock = 16384;
+  const size_t nb = (n + kBlock - 1) / kBlock;
+  if (nb <= 1 || workers_ <= 1) {
+    size_t w = 0;
+    for (size_t i = 0; i < n; ++i)
+      if (active_[act_[i]]) act_[w++] = act_[i];
+    act_.resize(w);
+    return;
+  }
+  // per block: the survivors' count; a prefix sum then gives each block its
+  // place in the output (order kept)
+  std::vector<size_t> cnt(nb + 1, 0);
+  parallel_for(nb, 1, workers_, [&](size_t b, int) {
+    size_t c = 0;
+    for (size_t i = b * kBlock; i < std::min(n, (b + 1) * kBlock); ++i) c += active_[act_[i]] != 0;
+    cnt[b + 1] = c;
+  });
+  for (size_t b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
+  std::vector<int32_t> out(cnt[nb]);
+  parallel_for(nb, 1, workers_, [&](size_t b, int) {
+    size_t w = cnt[b];
+    for (size_t i = b * kBlock; i < std::min(n, (b + 1) * kBlock); ++i)
+      if (active_[act_[i]]) out[w++] = act_[i];
+  });
+  act_.swap(out);
 }
 
 void Planner::adopt_level0(std::shared_ptr<const LevelPlan> p) {
@@ -448,9 +470,15 @@ void Planner::plan_cells(int l) {
   if (l == 0) building0_ = lp;
   lv_[l].plan = lp;
   lv_[l].res.clear();
-  for (const Cell& C : lp->cells)
-    for (int32_t d : C.p) active_[d] = 0;
+  // cells are disjoint: each byte is written by one cell
+  parallel_for(lp->cells.size(), 64, workers_, [&](size_t ci, int) {
+    for (int32_t d : lp->cells[ci].p) active_[d] = 0;
+  });
   drop_inactive();
+  if (l == 0) {   // the state adopt_level0 restores for later factorizations
+    active0_ = active_;
+    act0_ = act_;
+  }
 }
 
 void Planner::build_cells(int l, LevelPlan& lp) {
@@ -499,7 +527,9 @@ void Planner::build_cells(int l, LevelPlan& lp) {
   if (l > 0) {
     const Level& prev = lv_[l - 1];
     const int64_t Bp = g_.n / (g_.m << (l - 1));
-    for (size_t ci = 0; ci < prev.cells().size(); ++ci) {
+    // parents found in parallel, lists filled in order
+    std::vector<int32_t> kpar(prev.cells().size()), gpar(prev.groups().size(), -1);
+    parallel_for(kpar.size(), 256, workers_, [&](size_t ci, int) {
       int64_t pb = prev.cells()[ci].cid, parent_box = 0, mul = 1;
       for (int k = 0; k < g_.dim; ++k) {
         int64_t bk = pb % Bp;
@@ -507,17 +537,20 @@ void Planner::build_cells(int l, LevelPlan& lp) {
         parent_box += (top ? 0 : (bk / 2)) * mul;
         mul *= B;
       }
-      int32_t pc = cell_of_box[parent_box];
+      const int32_t pc = cell_of_box[parent_box];
       if (pc < 0) throw std::runtime_error("planner: parent box without interior");
-      kids[pc].push_back(int32_t(ci));
-    }
-    for (size_t gi = 0; gi < prev.groups().size(); ++gi) {
+      kpar[ci] = pc;
+    });
+    parallel_for(gpar.size(), 256, workers_, [&](size_t gi, int) {
       const auto& surv = prev.survivors(gi);
-      if (surv.empty()) continue;
-      int64_t d0 = surv[0];
-      if (!interior(d0)) continue;
-      gkids[cell_of_box[box_of(d0, l)]].push_back(int32_t(gi));
-    }
+      if (surv.empty()) return;
+      const int64_t d0 = surv[0];
+      if (!interior(d0)) return;
+      gpar[gi] = cell_of_box[box_of(d0, l)];
+    });
+    for (size_t ci = 0; ci < kpar.size(); ++ci) kids[kpar[ci]].push_back(int32_t(ci));
+    for (size_t gi = 0; gi < gpar.size(); ++gi)
+      if (gpar[gi] >= 0) gkids[gpar[gi]].push_back(int32_t(gi));
   }
 
   tm.mark("children");
