@@ -667,35 +667,48 @@ static SrcDev resolve(const hifde_factor_s& F, const Source& s) {
   return d;
 }
 
-static void append_trips(std::vector<TripDev>& out, const std::vector<Trip>& in) {
-  for (const Trip& t : in) out.push_back({t.i, t.j, t.ref});
-}
-
 // `one_launch`: also plan the upward step of both colors in one launch.
 static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, const LevelPlan& lp,
                                                     bool one_launch) {
   auto cs = std::make_shared<CellStatic>();
-  int64_t off = 0;
-  for (const Cell& c : lp.cells) {
-    FrontDev f{};
+  const size_t nc = lp.cells.size();
+  // offsets first (in order), then every cell's lists in parallel
+  cs->fh.resize(nc);
+  int64_t off = 0, nsrc = 0, ntrip = 0, nidx = 0;
+  for (size_t ci = 0; ci < nc; ++ci) {
+    const Cell& c = lp.cells[ci];
+    FrontDev& f = cs->fh[ci];
+    f = FrontDev{};
     f.off = off;
     f.p = int32_t(c.p.size());
     f.s = int32_t(c.p.size() + c.q.size());
-    f.src_begin = int32_t(cs->srcs_h.size());
-    for (const Source& s : c.src) cs->srcs_h.push_back(resolve(F, s));
-    f.src_end = int32_t(cs->srcs_h.size());
-    f.trip_begin = int64_t(cs->trips_h.size());
-    append_trips(cs->trips_h, c.trips);
-    f.trip_end = int64_t(cs->trips_h.size());
-    f.idx = int64_t(cs->idx_h.size());
-    cs->idx_h.insert(cs->idx_h.end(), c.p.begin(), c.p.end());
-    cs->idx_h.insert(cs->idx_h.end(), c.q.begin(), c.q.end());
+    f.src_begin = int32_t(nsrc);
+    nsrc += int64_t(c.src.size());
+    f.src_end = int32_t(nsrc);
+    f.trip_begin = ntrip;
+    ntrip += int64_t(c.trips.size());
+    f.trip_end = ntrip;
+    f.idx = nidx;
+    nidx += f.s;
     f.color = c.color;
     off += int64_t(f.s) * f.s;
     cs->pmax = std::max(cs->pmax, f.p);
     cs->smax = std::max(cs->smax, f.s);
-    cs->fh.push_back(f);
   }
+  cs->srcs_h.resize(size_t(nsrc));
+  cs->trips_h.resize(size_t(ntrip));
+  cs->idx_h.resize(size_t(nidx));
+  plan_parallel(nc, 16, [&](size_t ci) {
+    const Cell& c = lp.cells[ci];
+    const FrontDev& f = cs->fh[ci];
+    for (size_t k = 0; k < c.src.size(); ++k) cs->srcs_h[size_t(f.src_begin) + k] = resolve(F, c.src[k]);
+    for (size_t k = 0; k < c.trips.size(); ++k) {
+      const Trip& t = c.trips[k];
+      cs->trips_h[size_t(f.trip_begin) + k] = TripDev{t.i, t.j, t.ref};
+    }
+    std::copy(c.p.begin(), c.p.end(), cs->idx_h.begin() + f.idx);
+    std::copy(c.q.begin(), c.q.end(), cs->idx_h.begin() + f.idx + int64_t(c.p.size()));
+  });
   cs->elems = off;
   cs->ncell = int(cs->fh.size());
   cs->maps_h = &lp.maps;
@@ -719,39 +732,65 @@ static void upload_cell_static(CellStatic& cs, Arena& mem, hipStream_t st) {
 static std::shared_ptr<GroupStatic> make_group_static(const hifde_factor_s& F,
                                                       const LevelPlan& lp, bool skel) {
   auto gs = std::make_shared<GroupStatic>();
-  int64_t base_off = 0, gw_off = 0, t_off = 0;
-  for (const Group& g : lp.groups) {
-    GroupDev d{};
+  const size_t ng = lp.groups.size();
+  // offsets first (in order), then every group's lists in parallel
+  gs->gh.resize(ng);
+  gs->bf.resize(ng);
+  int64_t base_off = 0, gw_off = 0, t_off = 0, nbs = 0, nbt = 0, ngs = 0, ngt = 0;
+  for (size_t gi = 0; gi < ng; ++gi) {
+    const Group& g = lp.groups[gi];
+    GroupDev& d = gs->gh[gi];
+    d = GroupDev{};
     d.nc = int32_t(g.c.size());
     d.nn = int32_t(g.cN.size());
     d.base_off = base_off;
     d.gw_off = gw_off;
     d.t_off = t_off;
-    FrontDev f{};
+    FrontDev& f = gs->bf[gi];
+    f = FrontDev{};
     f.off = base_off;
     f.s = d.nc;
     f.p = 0;
-    f.src_begin = int32_t(gs->bsrcs_h.size());
-    for (const Source& s : g.bsrc) gs->bsrcs_h.push_back(resolve(F, s));
-    f.src_end = int32_t(gs->bsrcs_h.size());
-    f.trip_begin = int64_t(gs->btrips_h.size());
-    append_trips(gs->btrips_h, g.btrips);
-    f.trip_end = int64_t(gs->btrips_h.size());
-    gs->bf.push_back(f);
-    d.src_begin = int32_t(gs->gsrcs_h.size());
-    for (const Source& s : g.gsrc) gs->gsrcs_h.push_back(resolve(F, s));
-    d.src_end = int32_t(gs->gsrcs_h.size());
-    d.trip_begin = int64_t(gs->gtrips_h.size());
-    append_trips(gs->gtrips_h, g.gtrips);
-    d.trip_end = int64_t(gs->gtrips_h.size());
+    f.src_begin = int32_t(nbs);
+    nbs += int64_t(g.bsrc.size());
+    f.src_end = int32_t(nbs);
+    f.trip_begin = nbt;
+    nbt += int64_t(g.btrips.size());
+    f.trip_end = nbt;
+    d.src_begin = int32_t(ngs);
+    ngs += int64_t(g.gsrc.size());
+    d.src_end = int32_t(ngs);
+    d.trip_begin = ngt;
+    ngt += int64_t(g.gtrips.size());
+    d.trip_end = ngt;
     base_off += int64_t(d.nc) * d.nc;
     if (skel) {
       gw_off += (int64_t(d.nn) + d.nc) * d.nc;
       t_off += int64_t(d.nc) * d.nc / 4 + 1;  // k (n-k) <= n^2/4
     }
     gs->ncmax = std::max(gs->ncmax, int(d.nc));
-    gs->gh.push_back(d);
   }
+  gs->bsrcs_h.resize(size_t(nbs));
+  gs->btrips_h.resize(size_t(nbt));
+  gs->gsrcs_h.resize(size_t(ngs));
+  gs->gtrips_h.resize(size_t(ngt));
+  plan_parallel(ng, 16, [&](size_t gi) {
+    const Group& g = lp.groups[gi];
+    const GroupDev& d = gs->gh[gi];
+    const FrontDev& f = gs->bf[gi];
+    for (size_t k = 0; k < g.bsrc.size(); ++k)
+      gs->bsrcs_h[size_t(f.src_begin) + k] = resolve(F, g.bsrc[k]);
+    for (size_t k = 0; k < g.btrips.size(); ++k) {
+      const Trip& t = g.btrips[k];
+      gs->btrips_h[size_t(f.trip_begin) + k] = TripDev{t.i, t.j, t.ref};
+    }
+    for (size_t k = 0; k < g.gsrc.size(); ++k)
+      gs->gsrcs_h[size_t(d.src_begin) + k] = resolve(F, g.gsrc[k]);
+    for (size_t k = 0; k < g.gtrips.size(); ++k) {
+      const Trip& t = g.gtrips[k];
+      gs->gtrips_h[size_t(d.trip_begin) + k] = TripDev{t.i, t.j, t.ref};
+    }
+  });
   gs->base_elems = base_off;
   gs->gw_elems = gw_off;
   gs->t_elems = t_off;

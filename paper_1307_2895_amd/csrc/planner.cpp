@@ -878,6 +878,10 @@ void Planner::finish_groups(int l) {
   drop_inactive();
 }
 
+void plan_parallel(size_t n, size_t grain, const std::function<void(size_t)>& f) {
+  parallel_for(n, grain, PlanPool::get().size(), [&](size_t i, int) { f(i); });
+}
+
 void discard_planner(std::unique_ptr<Planner> p) {
   if (p) Janitor::get().discard(std::move(p));
 }

@@ -23,6 +23,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -173,6 +174,10 @@ class Planner {
 
 // Frees a planner on a background thread (host memory only).
 void discard_planner(std::unique_ptr<Planner> p);
+
+// f(i) for i in [0, n) on the planner's thread pool, `grain` items at a
+// time (the first exception is rethrown).
+void plan_parallel(size_t n, size_t grain, const std::function<void(size_t)>& f);
 
 // Validates a tree request; returns an empty string when valid.
 std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out);
