@@ -840,18 +840,27 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
   if (fh.empty()) return;
   int pmax = 0;
   for (const auto& f : fh) pmax = std::max(pmax, f.p);
-  for (int j0 = 0; j0 < pmax; j0 += kNB) {
-    const unsigned nf = active_fronts(fh, j0, sorted);
-    if (nf == 0) break;
-    int64_t maxt = 0, maxr = 0;
+  // Tiles of an update whose trailing block starts `w` columns after j0
+  // (w(f) = columns applied); `first_col`: the first tile column only.
+  auto tiles = [&](int j0, int width, bool first_col) {
+    int64_t mt = 0;
     for (const auto& f : fh) {
       if (j0 >= f.p) continue;
-      int r0 = bounds ? j0 + 1 : std::min(j0 + kNB, f.p);
-      int64_t nt = f.s - r0;
+      const int r0 = bounds ? j0 + 1 : j0 + std::min(width, f.p - j0);
+      const int64_t nt = f.s - r0;
       if (nt <= 0) continue;
-      int64_t T_ = (nt + kTB - 1) / kTB;
-      maxt = std::max(maxt, T_ * (T_ + 1) / 2);
-      maxr = std::max(maxr, (nt + 63) / 64);
+      const int64_t T_ = (nt + kTB - 1) / kTB;
+      mt = std::max(mt, first_col ? T_ : T_ * (T_ + 1) / 2);
+    }
+    return mt;
+  };
+  auto panel = [&](int j0) {   // diagonal block and rows of panel j0
+    const unsigned nf = active_fronts(fh, j0, sorted);
+    int64_t maxr = 0;
+    for (const auto& f : fh) {
+      if (j0 >= f.p) continue;
+      const int r0 = bounds ? j0 + 1 : std::min(j0 + kNB, f.p);
+      if (f.s > r0) maxr = std::max<int64_t>(maxr, (f.s - r0 + 63) / 64);
     }
     // one wavefront per diagonal block: the 32 dependent steps are latency
     // bound, so many small work-groups per CU do better than few large ones
@@ -860,15 +869,36 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     if (maxr > 0)
       hipLaunchKernelGGL(k_ldl_rows<T>, dim3(front_tile_grid(nf, maxr, "panel grid")),
                          dim3(kThreads), 0, st, pool, fronts_d, j0, int(nf), int(maxr));
-    if (maxt > 0) {
-      const unsigned g = front_tile_grid(nf, maxt, "trailing-update grid");
-      if (variant == LDL_MFMA)
-        hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d,
-                           j0, int(nf), int(maxt));
-      else
-        hipLaunchKernelGGL(k_ldl_update<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, j0,
-                           int(nf), int(maxt));
+  };
+  auto update = [&](unsigned nf, int j0, int64_t mt, int mode) {
+    if (mt <= 0) return;
+    const unsigned g = front_tile_grid(nf, mt, "trailing-update grid");
+    if (variant == LDL_MFMA)
+      hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d,
+                         j0, int(nf), int(mt), mode);
+    else
+      hipLaunchKernelGGL(k_ldl_update<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, j0,
+                         int(nf), int(mt));
+  };
+  // panels in pairs (delayed update) on the matrix cores, one at a time
+  // otherwise.  Pairs start at multiples of 2 kNB whatever the counts (a
+  // pair without its second panel sums as a single update), so bounded and
+  // exact pivot counts give the same arithmetic.
+  const bool pairs = variant == LDL_MFMA;
+  for (int j0 = 0; j0 < pmax;) {
+    const unsigned nf = active_fronts(fh, j0, sorted);
+    if (nf == 0) break;
+    panel(j0);
+    const bool next = pairs && j0 + kNB < pmax;
+    if (!next) {
+      update(nf, j0, tiles(j0, kNB, false), 0);
+      j0 += kNB;
+      continue;
     }
+    update(nf, j0, tiles(j0, kNB, true), 1);          // panel j -> panel j+1's columns
+    panel(j0 + kNB);
+    update(nf, j0, tiles(j0, 2 * kNB, false), 2);     // panels j, j+1 -> the rest
+    j0 += 2 * kNB;
   }
   HIP_CHECK(hipGetLastError());
 }
