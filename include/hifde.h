@@ -174,7 +174,9 @@ int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
 
 /* Kernel timing.  Launches of the selected kernel classes are bracketed by
  * HIP events on the stream they run on (while profiling, F^-1 runs as direct
- * launches, not as the captured graph); hifde_profile_read reports, per
+ * launches, not as the captured graph, except with HIFDE_PROF_SWEEP_UP_ONE
+ * as the only class: that first kernel of each application always runs as a
+ * direct launch before the graph of the rest); hifde_profile_read reports, per
  * class, the launches timed, their summed event time and their algorithmic
  * traffic and flops (the bytes of the stored factor blocks, index lists and
  * vector rows the launch must touch, and the multiply-adds the sweep

@@ -126,3 +126,28 @@ def test_invalid_coefficients_rejected(prec, what):
     # the tree stays usable
     F = H.hifde_factor(T, torch_inputs(W.make_field(dim, n, "loguniform", 11)), None, 1e-6, prec)
     assert H.hifde_stats(F)["top_size"] > 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_timed_first_sweep_with_graph_matches_unprofiled(prec):
+    """Timing only the one-launch level-0 upward sweep runs that kernel
+    directly and the rest of each F^-1 application from a graph captured
+    without it; PCG must reproduce the unprofiled run bit for bit, and the
+    class must have timed one launch per application."""
+    import paper_1307_2895_amd as H
+    print(f"case prec={prec}", flush=True)
+    dim, n, m, nrhs = 2, 512, 8, 16
+    a = W.make_field(dim, n, "bernoulli_contrast", 7)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    f = torch.from_numpy(W.make_rhs(n ** dim, nrhs, 9)).cuda()
+    Fn = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+    un, itn, _ = H.hifde_pcg(Fn, f, tol=1e-10)
+    Fp = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+    H.hifde_profile(Fp, 1 << H.HIFDE_PROF_SWEEP_UP_ONE, -1)
+    up, itp, _ = H.hifde_pcg(Fp, f, tol=1e-10)
+    r = H.hifde_profile_read(Fp, H.HIFDE_PROF_SWEEP_UP_ONE)
+    torch.cuda.synchronize()
+    assert np.array_equal(itn, itp)
+    assert torch.equal(un, up)
+    assert r["launches"] == int(np.max(itp))   # one application before each iteration but the last
+    assert r["ms"] > 0 and r["bytes"] > 0
