@@ -2093,11 +2093,7 @@ static void apply_inverse_g(hifde_factor_s& F, TX* X, TX* Z, int nrhs, hipStream
       throw;
     }
     F.upc_part = 0;
-    if (!did) {   // no one-launch form here: every launch direct
-      apply_inverse<T, TX>(F, X, Z, nrhs, st);
-      return;
-    }
-    part = 2;
+    if (did) part = 2;   // else no one-launch form: the whole application from the graph
   }
   if (!(F.gexec && F.g_nrhs == nrhs && F.g_x == X && F.g_z == Z && F.g_c == F.C.p &&
         F.g_part == part)) {
