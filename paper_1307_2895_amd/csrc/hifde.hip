@@ -2319,8 +2319,15 @@ static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* co
   // (check_input): until then every kernel indexes by structure only, so
   // invalid values cannot make one fault
   F.bad_d = bad;
-  if (prec == HIFDE_MIXED) run_factor<float>(F, tree, st);
-  else run_factor<double>(F, tree, st);
+  {
+    // freed planners wait meanwhile (see planning_begin)
+    struct Planning {
+      Planning() { planning_begin(); }
+      ~Planning() { planning_end(); }
+    } planning;
+    if (prec == HIFDE_MIXED) run_factor<float>(F, tree, st);
+    else run_factor<double>(F, tree, st);
+  }
   F.join_side(st);
   HIP_CHECK(hipStreamSynchronize(st));
   check_input(F, st);

@@ -132,6 +132,8 @@ class PlanPool {
 
 // Frees finished planners on a background thread: their level plans are
 // many small host arrays, whose release would otherwise hold up the caller.
+// It waits while a factorization is planning (planning_begin/end): freeing
+// beside the planner's threads slowed their allocations.
 class Janitor {
  public:
   static Janitor& get() {
@@ -142,6 +144,13 @@ class Janitor {
     {
       std::lock_guard<std::mutex> lk(m_);
       q_.push_back(std::move(p));
+    }
+    cv_.notify_one();
+  }
+  void planning(int delta) {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      active_ += delta;
     }
     cv_.notify_one();
   }
@@ -159,8 +168,8 @@ class Janitor {
   void loop() {
     std::unique_lock<std::mutex> lk(m_);
     for (;;) {
-      cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
-      if (q_.empty()) return;   // stopping, nothing left
+      cv_.wait(lk, [&] { return stop_ || (!q_.empty() && active_ == 0); });
+      if (stop_ && (q_.empty() || active_ > 0)) return;   // stopping
       std::vector<std::unique_ptr<Planner>> batch;
       batch.swap(q_);
       lk.unlock();
@@ -171,6 +180,7 @@ class Janitor {
   std::mutex m_;
   std::condition_variable cv_;
   std::vector<std::unique_ptr<Planner>> q_;
+  int active_ = 0;   // factorizations planning
   bool stop_ = false;
   std::thread t_;   // last: starts once the members above exist
 };
@@ -881,6 +891,9 @@ void Planner::finish_groups(int l) {
 void plan_parallel(size_t n, size_t grain, const std::function<void(size_t)>& f) {
   parallel_for(n, grain, PlanPool::get().size(), [&](size_t i, int) { f(i); });
 }
+
+void planning_begin() { Janitor::get().planning(1); }
+void planning_end() { Janitor::get().planning(-1); }
 
 void discard_planner(std::unique_ptr<Planner> p) {
   if (p) Janitor::get().discard(std::move(p));

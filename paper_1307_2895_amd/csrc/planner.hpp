@@ -174,6 +174,10 @@ class Planner {
 
 // Frees a planner on a background thread (host memory only).
 void discard_planner(std::unique_ptr<Planner> p);
+// A factorization's planning starts / ends (discarded planners are freed
+// while none is planning).
+void planning_begin();
+void planning_end();
 
 // f(i) for i in [0, n) on the planner's thread pool, `grain` items at a
 // time (the first exception is rethrown).
