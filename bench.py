@@ -178,8 +178,8 @@ def main():
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
-              "the method's multi-GPU sharding is described in DESIGN.md and not built.",
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): "
+              "the path runs on one GPU; sharding it over several is not built.",
               file=sys.stderr)
         sys.exit(2)
     import torch
