@@ -1,6 +1,7 @@
 // HIF-DE on gfx950: C ABI, factorization driver (Algorithm 4.1), F^-1
 // application and preconditioned conjugate gradients.
 #include <functional>
+#include <future>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -585,6 +586,12 @@ struct hifde_factor_s {
   }
   // Releases the runtime handles (idempotent).
   void release_handles() {
+    if (skel_job.valid()) {   // (a failure elsewhere: its own error is moot)
+      try {
+        skel_job.get();
+      } catch (...) {
+      }
+    }
     // blocks go back to the pool for reuse: no kernel may still use them
     if (pool) (void)hipDeviceSynchronize();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -602,6 +609,13 @@ struct hifde_factor_s {
       if (e.b) (void)hipEventDestroy(e.b);
     }
     prof_ev.clear();
+  }
+  // A level's skeleton fronts, prepared and launched on a helper thread
+  // while the host plans the next level (join_skel before the arena, the
+  // stream or that level's descriptors are used again).
+  std::future<void> skel_job;
+  void join_skel() {
+    if (skel_job.valid()) skel_job.get();
   }
   ~hifde_factor_s() { release_handles(); }
 };
@@ -1086,15 +1100,18 @@ static std::vector<FrontDev> sorted_by_p(const std::vector<FrontDev>& fh) {
 
 template <typename T, typename TS>
 static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
-  F.flush_side(st);
   Planner& P = *F.planner;
   CellLevel& D = F.cl[l];
   PhaseTimer tm;
   if (l == 0 && tree->c0) {
+    F.join_skel();
+    F.flush_side(st);
     D.st = tree->c0;
   } else {
     if (l > 0) P.plan_cells(l);
     tm.mark("  plan cells", l);
+    F.join_skel();   // the previous level's skeleton fronts
+    F.flush_side(st);
     D.st = make_cell_static(F, *P.level(l).plan, l == 0);
     tm.mark("  cell descriptors", l);
     if (l == 0) {
@@ -1265,6 +1282,94 @@ static void launch_group_front(GroupLevel& G, int nblocks, int ncmax, const int3
                          G.perm, G.perm_stride, gsel, kdev, phase);
   }
   HIP_CHECK(hipGetLastError());
+}
+
+// The skeleton fronts of level l (Lemma 2.4) once its ranks are known: the
+// groups' lists, the fronts' assembly, elimination and apply form, and
+// their sweep descriptors.  Run on a helper thread beside the planning of
+// level l+1 (it uses the arena and the stream; the main thread waits for
+// it before it does).
+template <typename T>
+static void skeleton_fronts(hifde_factor_s& F, GroupLevel& G, const Level& lev,
+                           const std::vector<int32_t>& kh, int l, hipStream_t st) {
+  PhaseTimer tm;
+  int64_t fg_off = 0;
+  int rmax = 0;
+  {
+    size_t nidx = 0, nsk = 0;
+    for (int gi = 0; gi < G.ngroup; ++gi)
+      if (kh[gi] < G.gh[gi].nc) {
+        nidx += size_t(G.gh[gi].nc);
+        nsk += 1;
+      }
+    G.idx_h.reserve(nidx);
+    G.ff.reserve(nsk);
+    G.gsel_h.reserve(nsk);
+  }
+  for (int gi = 0; gi < G.ngroup; ++gi) {
+    GroupDev& d = G.gh[gi];
+    const int k = kh[gi];
+    d.k = k;
+    d.skel = (k < d.nc) ? 1 : 0;
+    if (!d.skel) continue;
+    d.fg_off = fg_off;
+    G.tel += double(k) * (d.nc - k);
+    G.rrows += d.nc - k;
+    G.krows += k;
+    rmax = std::max(rmax, d.nc - k);
+    FrontDev f{};
+    f.off = d.fg_off;
+    f.s = d.nc;
+    f.p = d.nc - k;
+    f.idx = int64_t(G.idx_h.size());
+    G.ff.push_back(f);
+    fg_off += int64_t(d.nc) * d.nc;
+    d.idx = int64_t(G.idx_h.size());
+    const GroupRes& R = lev.res[gi];
+    G.idx_h.insert(G.idx_h.end(), R.rd.begin(), R.rd.end());
+    G.idx_h.insert(G.idx_h.end(), R.sk.begin(), R.sk.end());
+    G.gsel_h.push_back(gi);
+    G.ncskel = std::max(G.ncskel, int(d.nc));
+  }
+  tm.mark("  skeleton lists", l);
+  G.nskel = int(G.gsel_h.size());
+  G.groups = F.mem.upload(G.gh, st);
+  if (G.nskel == 0) return;
+  G.idx = F.mem.upload(G.idx_h, st);
+  G.gsel = F.mem.upload(G.gsel_h, st);
+  G.fg = F.mem.get<T>(size_t(fg_off));
+  HIP_CHECK(hipMemsetAsync(G.fg, 0, size_t(fg_off) * sizeof(T), st));
+  G.fgfronts = F.mem.upload(G.ff, st);
+  G.info = F.mem.get<int>(G.ff.size());
+  HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ff.size(), st));
+  launch_group_front<T>(G, G.nskel, G.ncskel, G.gsel, static_cast<const int32_t*>(nullptr), st);
+  {
+    const std::vector<FrontDev> fs = sorted_by_p(G.ff);
+    const FrontDev* fs_d = F.mem.upload(fs, st);
+    int pmx = 0, smx = 0;
+    for (const FrontDev& f : fs) {
+      pmx = std::max(pmx, f.p);
+      smx = std::max(smx, f.s);
+    }
+    const int var = tune_choice(
+        F, tune_key(FAM_LDL, int(sizeof(T)), pmx, smx, G.nskel), LDL_VARIANTS, LDL_MFMA, G.fg,
+        size_t(fg_off) * sizeof(T), st, [&](int v) {
+          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, v);
+        });
+    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, var);
+    const int ivar = tune_choice(
+        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 2, 1, G.fg,
+        size_t(fg_off) * sizeof(T), st,
+        [&](int v) { apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, v); });
+    apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, ivar);
+  }
+  F.skel_panels += (rmax + kNB - 1) / kNB;
+  build_sweep(G.sw, G.ff, false);
+  for (size_t i = 0; i < G.sw.ph.size(); ++i) G.sw.ph[i].t_off = G.gh[G.gsel_h[i]].t_off;
+  upload_sweep(G.sw, F.mem, st);
+  pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.pt,
+                 &G.dinv, st);
+  tm.mark("  skeleton fronts", l);
 }
 
 template <typename T>
@@ -1520,6 +1625,14 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     if (kh[gi] < 0 || kh[gi] > G.gh[gi].nc) throw Error(HIFDE_EDEVICE, "ID returned an invalid rank");
   P.set_skeletons(l, kh.data(), ph.data(), size_t(ncmax));
   tm.mark("  set skeletons", l);
+  if (!pre) {
+    P.finish_groups(l);   // the planner's part: level l+1 can be planned now
+    tm.mark("  finish groups", l);
+    F.skel_job = std::async(std::launch::async, [&F, &G, &lev, kh = std::move(kh), l, st] {
+      skeleton_fronts<T>(F, G, lev, kh, l, st);
+    });
+    return;
+  }
   {
     size_t nidx = 0, nsk = 0;
     for (int gi = 0; gi < G.ngroup; ++gi)
@@ -1531,17 +1644,15 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     G.ff.reserve(nsk);
     G.gsel_h.reserve(nsk);
   }
+  // pre-launched skeleton fronts (their slots fixed before the IDs)
   for (int gi = 0; gi < G.ngroup; ++gi) {
     GroupDev& d = G.gh[gi];
     const int k = kh[gi];
-    if (pre) {
-      F.rank_groups += 1;
-      F.rank_abs_err += std::abs(double(khat[gi]) - double(k));
-    }
+    F.rank_groups += 1;
+    F.rank_abs_err += std::abs(double(khat[gi]) - double(k));
     d.k = k;
     d.skel = (k < d.nc) ? 1 : 0;
     if (!d.skel) continue;
-    if (!pre) d.fg_off = fg_off;
     G.tel += double(k) * (d.nc - k);
     G.rrows += d.nc - k;
     G.krows += k;
@@ -1565,7 +1676,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   tm.mark("  finish groups", l);
   G.nskel = int(G.gsel_h.size());
   G.groups = F.mem.upload(G.gh, st);
-  if (pre) {
+  {
     // a rank beyond the launched panels: eliminate every front again with
     // the actual bound (the IDs' choices are unchanged)
     if (rmax > pbound) {
@@ -1593,42 +1704,6 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     }
     return;
   }
-  if (G.nskel == 0) return;
-  G.idx = F.mem.upload(G.idx_h, st);
-  G.gsel = F.mem.upload(G.gsel_h, st);
-  G.fg = F.mem.get<T>(size_t(fg_off));
-  HIP_CHECK(hipMemsetAsync(G.fg, 0, size_t(fg_off) * sizeof(T), st));
-  G.fgfronts = F.mem.upload(G.ff, st);
-  G.info = F.mem.get<int>(G.ff.size());
-  HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ff.size(), st));
-  launch_group_front<T>(G, G.nskel, G.ncskel, G.gsel, static_cast<const int32_t*>(nullptr), st);
-  {
-    const std::vector<FrontDev> fs = sorted_by_p(G.ff);
-    const FrontDev* fs_d = F.mem.upload(fs, st);
-    int pmx = 0, smx = 0;
-    for (const FrontDev& f : fs) {
-      pmx = std::max(pmx, f.p);
-      smx = std::max(smx, f.s);
-    }
-    const int var = tune_choice(
-        F, tune_key(FAM_LDL, int(sizeof(T)), pmx, smx, G.nskel), LDL_VARIANTS, LDL_MFMA, G.fg,
-        size_t(fg_off) * sizeof(T), st, [&](int v) {
-          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, v);
-        });
-    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, var);
-    const int ivar = tune_choice(
-        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 2, 1, G.fg,
-        size_t(fg_off) * sizeof(T), st,
-        [&](int v) { apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, v); });
-    apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, ivar);
-  }
-  F.skel_panels += (rmax + kNB - 1) / kNB;
-  build_sweep(G.sw, G.ff, false);
-  for (size_t i = 0; i < G.sw.ph.size(); ++i) G.sw.ph[i].t_off = G.gh[G.gsel_h[i]].t_off;
-  upload_sweep(G.sw, F.mem, st);
-  pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), G.ff, G.fgfronts, G.sw, &G.pk, &G.pt,
-                 &G.dinv, st);
-  tm.mark("  skeleton fronts", l);
 }
 
 template <typename T>

@@ -68,8 +68,11 @@ class PlanPool {
 
  private:
   PlanPool() {
+    // two CPUs left to the factorization's other host threads (the
+    // skeleton-front helper, the HIP runtime's): a pool that fills every
+    // CPU stalls on them
     unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    int n = int(std::min(16u, hw));
+    int n = std::max(1, int(std::min(16u, hw)) - 2);
     if (const char* e = std::getenv("HIFDE_PLAN_THREADS")) n = std::max(1, std::atoi(e));
     for (int w = 1; w < n; ++w) threads_.emplace_back([this, w] { loop(w); });
   }
