@@ -2568,9 +2568,11 @@ int hifde_plan_replay(hifde_tree_t tree, const int32_t* redundant_level, hifde_f
           if (redundant_level[groups[gi].c[i]] != 2 * l + 1) pos[gi * stride + size_t(k++)] = i;
         ks[gi] = k;
       }
+      tm.mark("skeleton positions", l);
       P.set_skeletons(l, ks.data(), pos.data(), stride);
+      tm.mark("set skeletons", l);
       P.finish_groups(l);
-      tm.mark("skeletons", l);
+      tm.mark("finish groups", l);
     }
     P.plan_cells(F->g.L);
     F->prec = HIFDE_FP64;

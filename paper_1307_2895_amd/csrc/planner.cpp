@@ -291,6 +291,7 @@ Planner::Planner(const Geom& g, std::unique_ptr<PlanScratch> scratch) : g_(g) {
     own0_ = std::move(scratch->own0);
     own1_ = std::move(scratch->own1);
     act_ = std::move(scratch->act);
+    act_spare_ = std::move(scratch->act_spare);
     active_ = std::move(scratch->active);
     grouped_ = std::move(scratch->grouped);
     geo_ = std::move(scratch->geo);
@@ -338,6 +339,7 @@ std::unique_ptr<PlanScratch> Planner::take_scratch() {
   s->own0 = std::move(own0_);
   s->own1 = std::move(own1_);
   s->act = std::move(act_);
+  s->act_spare = std::move(act_spare_);
   s->active = std::move(active_);
   s->grouped = std::move(grouped_);
   s->geo = std::move(geo_);
@@ -350,6 +352,7 @@ std::unique_ptr<PlanScratch> Planner::take_scratch() {
   own0_.clear();
   own1_.clear();
   act_.clear();
+  act_spare_.clear();
   active_.clear();
   grouped_.clear();
   return s;
@@ -443,7 +446,10 @@ void Planner::drop_inactive() {
     cnt[b + 1] = c;
   });
   for (size_t b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
-  std::vector<int32_t> out(cnt[nb]);
+  // (into the spare array, whose memory is kept: a new one each time was
+  // most of the cost)
+  std::vector<int32_t>& out = act_spare_;
+  out.resize(cnt[nb]);
   parallel_for(nb, 1, workers_, [&](size_t b, int) {
     size_t w = cnt[b];
     for (size_t i = b * kBlock; i < std::min(n, (b + 1) * kBlock); ++i)
@@ -881,6 +887,7 @@ void Planner::set_skeletons(int l, const int32_t* ks, const int32_t* pos, size_t
 }
 
 void Planner::finish_groups(int l) {
+  PlanTimer tm("finish", l);
   const Level& lev = lv_[l];
   // groups are disjoint: each byte is written by one group
   parallel_for(lev.groups().size(), 64, workers_, [&](size_t gi, int) {
@@ -888,7 +895,9 @@ void Planner::finish_groups(int l) {
     if (lev.res[gi].skel)
       for (int32_t d : lev.res[gi].rd) active_[d] = 0;
   });
+  tm.mark("marks");
   drop_inactive();
+  tm.mark("compaction");
 }
 
 void plan_parallel(size_t n, size_t grain, const std::function<void(size_t)>& f) {

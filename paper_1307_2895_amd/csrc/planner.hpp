@@ -106,7 +106,7 @@ struct Level {
 // each time; the position maps are all -1 whenever no planning step runs.
 struct PlanScratch {
   std::vector<std::vector<int32_t>> loc;
-  std::vector<int32_t> own0, own1, act;
+  std::vector<int32_t> own0, own1, act, act_spare;
   std::vector<uint8_t> active, grouped;
   std::vector<uint32_t> geo;    // per unknown, geometry only (see Planner::geo_)
   // the active set once the tree's level-0 cells are eliminated
@@ -164,6 +164,7 @@ class Planner {
   std::vector<int32_t> act0_;
   std::vector<uint8_t> active_, grouped_;
   std::vector<int32_t> act_;         // sorted active unknowns
+  std::vector<int32_t> act_spare_;   // drop_inactive's output, swapped with act_
   int32_t* loc(int worker);           // worker's global -> local map (all -1)
   int workers_ = 1;                  // planning threads
   std::vector<std::vector<int32_t>> loc_;
