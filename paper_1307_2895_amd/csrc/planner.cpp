@@ -717,16 +717,20 @@ void Planner::build_groups(int l, LevelPlan& lp) {
   // Earlier bases that land in each group.
   std::vector<std::vector<int32_t>> gkids(lp.groups.size());
   if (l > 0) {
+    // parents found in parallel, lists filled in order
     const Level& prev = lv_[l - 1];
-    for (size_t gi = 0; gi < prev.groups().size(); ++gi) {
+    std::vector<int32_t> gpar(prev.groups().size(), -1);
+    parallel_for(gpar.size(), 256, workers_, [&](size_t gi, int) {
       const auto& surv = prev.survivors(gi);
-      if (surv.empty()) continue;
-      int32_t d0 = surv[0];
-      if (sigma(d0, l) != 1) continue;
-      int32_t g = group_of_key[group_key(d0, l)];
+      if (surv.empty()) return;
+      const int32_t d0 = surv[0];
+      if (sigma(d0, l) != 1) return;
+      const int32_t g = group_of_key[group_key(d0, l)];
       if (g < 0) throw std::runtime_error("planner: base without group");
-      gkids[g].push_back(int32_t(gi));
-    }
+      gpar[gi] = g;
+    });
+    for (size_t gi = 0; gi < gpar.size(); ++gi)
+      if (gpar[gi] >= 0) gkids[gpar[gi]].push_back(int32_t(gi));
   }
   tm.mark("children");
   std::vector<std::vector<int32_t>> gm(lp.groups.size());
