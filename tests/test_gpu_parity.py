@@ -97,3 +97,27 @@ def test_mixed_pcg_converges(dim, n, m, eps, field, seed):
     d = np.linalg.norm(OF.A @ (ug - uo), axis=0) / np.linalg.norm(f, axis=0)
     assert np.all(d <= 1e-10), d
     print("mixed iters", its, "oracle fp64 iters", ito)
+
+
+# Right-hand-side counts that change the PCG passes' 2D strips: 5 columns run
+# one column per lane (strips 51 unknowns wide, one per row of 48), 34 run
+# pairs of columns (strips 15 wide: four per row, the last one ragged).
+@pytest.mark.parametrize("mixed", [0, 1])
+@pytest.mark.parametrize("nrhs", [5, 34])
+def test_pcg_ragged_strips_match_oracle(mixed, nrhs):
+    import paper_1307_2895_amd as H
+    dim, n, m, eps = 2, 48, 3, 1e-6
+    print(f"case n={n} leaf={m} nrhs={nrhs} mixed={mixed}", flush=True)
+    a = W.make_field(dim, n, "loguniform", 7)
+    OF = oracle_factor(dim, n, m, a, eps)
+    T, F = gpu_factor(dim, n, m, a, eps, mixed)
+    f = W.make_rhs(n ** dim, nrhs, 17)
+    ug, its, rel = H.hifde_pcg(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=200)
+    ug = ug.cpu().numpy()
+    assert np.all(rel <= 1.5e-12), rel
+    uo, ito, _ = OP.pcg_multi(OF.A, f, lambda r: OH.solve(OF, r), 1e-12, 200)
+    d = np.linalg.norm(OF.A @ (ug - uo), axis=0) / np.linalg.norm(f, axis=0)
+    assert np.all(d <= 1e-10), d
+    print("iters gpu", its, "oracle", ito)
+    if not mixed:
+        assert np.all(np.abs(its - ito) <= 1)
