@@ -2267,11 +2267,9 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   double* beta = sc + 2 * nr;
   double* d1 = sc + 3 * nr;
   int* live = reinterpret_cast<int*>(sc + 8 * nr);
-  const unsigned nb = kPcgBlocks;
   const unsigned nb_ap = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_ap<TR, W, DIM>));
   const unsigned nb_xr = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_xr<TR, W, DIM>));
   const unsigned nb_rz = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_rz<TR, W>));
-  const int dim = F.g.dim;
   const int64_t side = F.g.n;
   const DivN dn = make_divn(uint32_t(side));
   const double* diag = F.diag.as<double>();
@@ -2334,13 +2332,12 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
     hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb_rz), int(nb_xr), nr,
                        pz, px, flexible, rz, live, beta);
   }
-  // true residuals ||f - A x|| (A x into pb, f into r)
-  hipLaunchKernelGGL(k_matvec, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, dim, side, diag, offd,
-                     x, pb);
-  hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
-                     r);
-  hipLaunchKernelGGL(k_pcg_resid, dim3(nb), dim3(kThreads), 0, st, N, nr, r, pb, px);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, px, d1);
+  // true residuals ||f - A x||, in one pass over x and f
+  const unsigned nb_tr =
+      pcg_blocks(reinterpret_cast<const void*>(&k_pcg_true_resid<W, DIM>));
+  hipLaunchKernelGGL((k_pcg_true_resid<W, DIM>), dim3(nb_tr), dim3(kThreads), 0, st, N, nr, dn,
+                     diag, offd, x, f, ldf, px);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_tr), nr, 0, px, d1);
   HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
   hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, x, u, ldu);
   HIP_CHECK(hipGetLastError());
