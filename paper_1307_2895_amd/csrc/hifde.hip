@@ -2275,16 +2275,14 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   const double* diag = F.diag.as<double>();
   const double* offd = F.offd.as<double>();
 
-  hipLaunchKernelGGL(k_from_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, f, ldf,
-                     r);
-  HIP_CHECK(hipMemsetAsync(x, 0, vbytes, st));
   HIP_CHECK(hipMemsetAsync(pa, 0, vbytes, st));
   HIP_CHECK(hipMemsetAsync(alpha, 0, size_t(nr) * 8, st));
   HIP_CHECK(hipMemsetAsync(rz, 0, size_t(nr) * 8, st));
-  // ||f||^2 and the preconditioner's copy of r (alpha = 0: x, r unchanged)
-  hipLaunchKernelGGL((k_pcg_xr<TR, W, DIM>), dim3(nb_xr), dim3(kThreads), 0, st, N, nr, dn, diag,
-                     offd, alpha, pa, x, r, rc, 0, px);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_xr), nr, 0, px, d1);
+  // r = f, the preconditioner's copy of r, x = 0 and ||f||^2
+  const unsigned nb_st = pcg_blocks(reinterpret_cast<const void*>(&k_pcg_start<TR, W>));
+  hipLaunchKernelGGL((k_pcg_start<TR, W>), dim3(nb_st), dim3(kThreads), 0, st, N, nr, f, ldf, x, r,
+                     rc, px);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_st), nr, 0, px, d1);
   std::vector<int> liveh(nr, 1), itsh(nr, 0);
   std::vector<double> fh(nr), h1(nr);
   HIP_CHECK(hipMemcpyAsync(fh.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
