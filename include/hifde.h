@@ -159,7 +159,8 @@ int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
  * from u = 0, in double precision, one independent iteration per column,
  * until ||f - A u|| <= tol ||f|| (recursive residual) or maxit iterations.
  * The mixed-precision factor uses the flexible (Polak-Ribiere) update.
- * f, u: DEVICE, N x nrhs column-major.  iters[nrhs], relres[nrhs]: HOST,
+ * f, u: DEVICE, N x nrhs column-major; f may equal u when ldf == ldu (no
+ * other overlap).  iters[nrhs], relres[nrhs]: HOST,
  * filled with the iteration count and the true relative residual
  * ||f - A u|| / ||f|| of each column.
  * ENOCONV: some column missed tol; iters, relres and u hold the last iterate. */

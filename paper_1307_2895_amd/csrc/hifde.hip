@@ -2330,14 +2330,13 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
     hipLaunchKernelGGL(k_reduce_beta, dim3(nr), dim3(kThreads), 0, st, int(nb_rz), int(nb_xr), nr,
                        pz, px, flexible, rz, live, beta);
   }
-  // true residuals ||f - A x||, in one pass over x and f
+  // true residuals ||f - A x|| and u = x, in one pass over x and f
   const unsigned nb_tr =
       pcg_blocks(reinterpret_cast<const void*>(&k_pcg_true_resid<W, DIM>));
   hipLaunchKernelGGL((k_pcg_true_resid<W, DIM>), dim3(nb_tr), dim3(kThreads), 0, st, N, nr, dn,
-                     diag, offd, x, f, ldf, px);
+                     diag, offd, x, f, ldf, u, ldu, px);
   hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_tr), nr, 0, px, d1);
   HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
-  hipLaunchKernelGGL(k_to_colmajor<double>, dim3(nblk(n)), dim3(kThreads), 0, st, N, nr, x, u, ldu);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
   bool converged = true;
