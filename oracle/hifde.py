@@ -26,7 +26,8 @@ Pinned by: eps=0 reproduces a sparse direct solve (tests/test_oracle_hifde.py),
 the block-diagonalizations of Lemmas 2.1 and 2.4 on random matrices, the ID
 against LAPACK's pivoted QR and exact low-rank reconstruction, symmetry and
 positive definiteness of F, the eigenvalue bound of Theorem 4.1's corollary,
-the partition of the unknowns, and e_a = O(eps).
+the partition of the unknowns, e_a = O(eps), and the flop count against
+closed-form sizes of the one-level tree.
 """
 from __future__ import annotations
 
@@ -242,13 +243,8 @@ def _add_blocks(A: sp.csr_matrix, blocks) -> sp.csr_matrix:
 # ---------------------------------------------------------------------------
 
 def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
-           skip_levels: int = 0, tau: float = 1e-10,
-           replay_skeletons=None) -> Factor:
-    """HIF-DE factorization ``A ~= V_0^-T ... V_{L-1/2}^-T D V_{L-1/2}^-1 ... V_0^-1``.
-
-    ``replay_skeletons`` (optional) maps ``(level, group_id)`` to a sorted
-    skeleton set, overriding the ID's choice (for comparisons that must keep
-    downstream levels on identical index sets)."""
+           skip_levels: int = 0, tau: float = 1e-10) -> Factor:
+    """HIF-DE factorization ``A ~= V_0^-T ... V_{L-1/2}^-T D V_{L-1/2}^-1 ... V_0^-1``."""
     if eps < 0 or eps >= 1:
         raise ValueError("eps must lie in [0, 1)")
     L = tree.num_levels(n, m)
@@ -284,18 +280,6 @@ def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
                 Mblk = _sub(A, cN, c)
                 idr = interp_decomp(Mblk, eps, tau)
                 k = idr.k
-                if replay_skeletons is not None and (lvl, gid) in replay_skeletons:
-                    sk_set = np.asarray(replay_skeletons[(lvl, gid)])
-                    pos = np.searchsorted(c, sk_set)
-                    rest = np.setdiff1d(np.arange(c.size), pos)
-                    perm = np.concatenate([pos, rest])
-                    k = pos.size
-                    sub = Mblk[:, perm]
-                    if 0 < k < c.size:
-                        T_piv = np.linalg.lstsq(sub[:, :k], sub[:, k:], rcond=None)[0]
-                    else:
-                        T_piv = np.zeros((k, c.size - k))
-                    idr = IDResult(k, perm, T_piv, idr.rdiag)
                 if k == c.size:
                     do_skel = False
             if not do_skel:
@@ -455,14 +439,20 @@ def partition_sizes(F: Factor) -> int:
 
 def factor_flops(F: Factor) -> float:
     """Algorithmic flop count of the factorization (dense-block model):
-    cells ``p^3/3 + p^2 q + p q^2``; groups ``2|c^N||c|k + r^3/3 + 5 k r^2 + 4 k^2 r``;
-    top ``|s_L|^3/3``."""
+    cells ``p^3/3 + p^2 q + p q^2`` (Lemma 2.1: the LDL^T of A_pp, W and the
+    Schur update of the front); skeletonized groups
+    ``2|c^N||c|k + r^3/3 + 5 k r^2 + 4 k^2 r`` (the ID of Section 2.2 and
+    Lemma 2.4's B_rr, B_sr, LDL^T and update); top ``|s_L|^3/3``.  A group
+    that keeps all of ``c`` (k = |c|, or no ID at eps = 0 and on skipped
+    levels) is left alone and counts nothing."""
     fl = F.top.p.size ** 3 / 3.0
     for lev in F.levels:
         for c in lev.cells:
             p, q = c.p.size, c.q.size
             fl += p ** 3 / 3.0 + p * p * q + p * q * q
         for g in lev.groups:
+            if not g.skeletonized:
+                continue
             k, r = g.sk.size, g.rd.size
             fl += 2.0 * g.cN.size * g.c.size * k + r ** 3 / 3.0 + 5.0 * k * r * r + 4.0 * k * k * r
     return fl

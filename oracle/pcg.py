@@ -9,6 +9,12 @@ symmetric.  Columns of a multi-column right-hand side are independent.
 Pinned by: with an exact preconditioner (eps = 0) the first iterate solves
 the system; on a diagonal test matrix the iterates match the closed form of
 CG; convergence to the requested tolerance (tests/test_oracle_pcg.py).
+
+Parity unpinned: the iteration path of the ``flexible`` variant under a
+preconditioner that is not symmetric.  With a symmetric one it equals the
+standard update (pinned); otherwise no closed form or library routine fixes
+its iterates, so only its converged solution (true residual at tol) is
+checked.
 """
 from __future__ import annotations
 

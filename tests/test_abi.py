@@ -148,3 +148,17 @@ def test_plan_replay_rejects_null_tree():
     out = C.c_void_p()
     rc = H.lib().hifde_plan_replay(None, None, C.byref(out))
     assert rc == H.HIFDE_EINVAL
+
+
+@pytest.mark.parametrize("dim,n,m,eps,field,seed,skip", REPLAY_CASES)
+def test_plan_replay_flop_count_matches_oracle(dim, n, m, eps, field, seed, skip):
+    """The library's algorithmic flop count (reported by hifde_stats and used
+    for every factorization rate) equals the oracle's factor_flops when both
+    hold the same index sets."""
+    import paper_1307_2895_amd as H
+    a = W.make_field(dim, n, field, seed)
+    OF = OH.factor(dim, n, m, a, eps=eps, skip_levels=skip)
+    T = H.hifde_build_tree(dim, n, m, skip)
+    P = H.hifde_plan_replay(T, _redundant_levels(OF))
+    st = H.hifde_stats(P)
+    assert st["factor_flops"] == pytest.approx(OH.factor_flops(OF), rel=1e-12)

@@ -238,3 +238,70 @@ def test_paper_magnitudes():
     assert 0.5 * row["sL"] <= F.top_size <= 1.5 * row["sL"]
     ea = OE.e_a(F.A, lambda v: OH.apply(F, v))
     assert row["e_a"] / 100 <= ea <= row["e_a"] * 10
+
+
+# ---------------------------------------------------------------- flop count
+def _one_level_closed_form(dim, m):
+    """Sizes of the one-level tree n = 2m (Section 3.1's geometry): the
+    2^dim cells have extents e_j in {m-1, m} (the last box per axis holds
+    one more row), interiors p = prod e_j and fronts q = sum_k prod_{j!=k}
+    e_j (the separator faces they touch; corner lines are not stencil
+    neighbours of an interior).  Each separator face on plane k with
+    extents e_j (j != k) has |c| = prod e_j and, after the cells are
+    eliminated, |c^N| = 2m sum_j prod_{i!=j} e_i: the other faces of its two
+    cells ((2m-1) e per crossing axis) plus the corner-line unknowns next
+    to it (one e per crossing axis)."""
+    import itertools
+    ext = (m - 1, m)
+    cells = []
+    for idx in itertools.product((0, 1), repeat=dim):
+        e = [ext[i] for i in idx]
+        p = int(np.prod(e))
+        q = sum(int(np.prod([e[j] for j in range(dim) if j != k])) for k in range(dim))
+        cells.append((p, q))
+    groups = []
+    for k in range(dim):
+        others = [j for j in range(dim) if j != k]
+        for idx in itertools.product((0, 1), repeat=dim - 1):
+            e = [ext[i] for i in idx]
+            c = int(np.prod(e))
+            cN = 2 * m * sum(int(np.prod([e[i] for i in range(len(e)) if i != j]))
+                             for j in range(len(e)))
+            groups.append((c, cN))
+    return cells, groups
+
+
+@pytest.mark.parametrize("dim,m,eps,field", [(2, 8, 0.0, "const"), (2, 8, 1e-6, "const"),
+                                             (2, 7, 1e-4, "loguniform"), (3, 4, 0.0, "const"),
+                                             (3, 4, 1e-6, "loguniform")])
+def test_factor_flops_closed_form_one_level(dim, m, eps, field):
+    """factor_flops on n = 2m (one level) equals the dense-block count
+    written from the closed-form sizes: cells p^3/3 + p^2 q + p q^2 (Lemma
+    2.1), skeletonized groups 2|c^N||c|k + r^3/3 + 5kr^2 + 4k^2r (Section
+    2.2 and Lemma 2.4) and the top |s_L|^3/3, |s_L| = N - sum p - sum r.
+    The group ranks k are the oracle's (the count takes them as given)."""
+    n = 2 * m
+    a = W.make_field(dim, n, field, 3)
+    F = OH.factor(dim, n, m, a, eps=eps)
+    cells, groups = _one_level_closed_form(dim, m)
+    assert F.L == 1
+    got_cells = sorted((c.p.size, c.q.size) for c in F.levels[0].cells)
+    assert got_cells == sorted(cells)
+    got_groups = sorted((g.c.size, g.cN.size) for g in F.levels[0].groups)
+    assert got_groups == sorted(groups)
+    fl = sum(p ** 3 / 3.0 + p * p * q + p * q * q for p, q in cells)
+    red = 0
+    for g in F.levels[0].groups:
+        c, k = g.c.size, g.sk.size
+        assert g.skeletonized == (eps > 0 and k < c)
+        if g.skeletonized:
+            r = c - k
+            cN = g.cN.size          # equals the closed form (multisets compared above)
+            fl += 2.0 * cN * c * k + r ** 3 / 3.0 + 5.0 * k * r * r + 4.0 * k * k * r
+            red += r
+    top = n ** dim - sum(p for p, _ in cells) - red
+    assert F.top_size == top
+    fl += top ** 3 / 3.0
+    assert OH.factor_flops(F) == pytest.approx(fl, rel=1e-12)
+    if eps == 0.0:
+        assert top == (2 * m) ** dim - (2 * m - 1) ** dim

@@ -32,3 +32,40 @@ def test_hifde_preconditioner_converges():
     for flexible in (False, True):
         X, its, rr = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 100, flexible)
         assert np.all(rr <= 2e-12) and np.all(its <= 19)
+
+
+def test_flexible_equals_standard_with_symmetric_preconditioner():
+    """With a symmetric preconditioner r_new^T z_old = 0 in exact arithmetic
+    (the preconditioned residuals are conjugate), so the flexible update is
+    the standard one: same iteration counts, same iterates to rounding."""
+    a = W.make_field(2, 32, "loguniform", 4)
+    F = OH.factor(2, 32, 4, a, eps=1e-4)
+    f = W.make_rhs(F.N, 2, 5)
+    Xs, its_s, _ = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 100, False)
+    Xf, its_f, _ = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 100, True)
+    assert np.array_equal(its_s, its_f)
+    assert np.max(np.abs(Xs - Xf)) <= 1e-10 * np.max(np.abs(Xs))
+
+
+def test_flexible_converges_with_nonsymmetric_preconditioner():
+    """A preconditioner that is not symmetric (F^-1 followed by a small
+    skew perturbation): the flexible variant still reaches the solution of a
+    sparse direct solve."""
+    import scipy.sparse.linalg as spla
+    a = W.make_field(2, 32, "loguniform", 6)
+    F = OH.factor(2, 32, 4, a, eps=1e-4)
+    rng = np.random.default_rng(7)
+    S = rng.standard_normal((F.N, 8))
+    K = 1e-3 * (S[:, :4] @ S[:, 4:].T - S[:, 4:] @ S[:, :4].T) / F.N
+
+    def prec(r):
+        z = OH.solve(F, r)
+        return z + K @ z
+
+    f = W.make_rhs(F.N, 1, 8)[:, 0]
+    z1, z2 = prec(f), prec(f[::-1].copy())
+    assert abs(f[::-1] @ z1 - f @ z2) > 1e-12 * abs(f @ z1)      # really not symmetric
+    x, it, rr = OP.pcg(F.A, f, prec, 1e-12, 200, flexible=True)
+    xd = spla.spsolve(F.A.tocsc(), f)
+    assert rr <= 2e-12
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
