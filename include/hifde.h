@@ -258,6 +258,21 @@ int hifde_mlp_grad(const float* params, int64_t nbatch, const float* feat,
                    const float* target, float* grad, float* loss, void* work,
                    void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the gradient of
+ * hifde_mlp_grad without the work argument.  The workspace is a static
+ * device array of (4 * HIFDE_RANK_HIDDEN + 2) * 4 bytes per sample for up to
+ * HIFDE_MLP_NOALLOC_MAX_BATCH samples (1032 bytes each, 8.45 MB in all),
+ * which each device holds from the first call on it until the process ends.
+ * The call allocates nothing.  All calls on one device share that array:
+ * calls that overlap in time on one device (two streams, two threads) race
+ * and give undefined results.  Results equal those of hifde_mlp_grad.
+ * EINVAL: NULL pointers, nbatch < 1 or nbatch > HIFDE_MLP_NOALLOC_MAX_BATCH. */
+#define HIFDE_MLP_NOALLOC_MAX_BATCH 8192
+int hifde_mlp_grad_noalloc(const float* params, int64_t nbatch, const float* feat,
+                           const float* target, float* grad, float* loss,
+                           void* hip_stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, epsilon 1e-8, bias-corrected;
  * step counts from 1) on params with moments m, v. */
 int hifde_mlp_adam(float* params, const float* grad, float* m, float* v,

@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     HIFDE_PROF_SWEEP_UP_WHOLE, HIFDE_PROF_SWEEP_DOWN_WHOLE, HIFDE_PROF_GROUP_UP,
     HIFDE_PROF_GROUP_DOWN, HIFDE_PROF_SWEEP_UP_ONE, HIFDE_PROF_CONTRIB_ADD,
     HIFDE_PROF_CLASSES, HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN, HIFDE_RANK_PARAMS,
+    HIFDE_MLP_NOALLOC_MAX_BATCH,
 )
 
 
@@ -235,6 +236,17 @@ def hifde_mlp_grad(params, feat, target, stream=None):
                                _f32(feat, (B, HIFDE_RANK_FEATURES)), _f32(target, (B,)),
                                _f32(g), _f32(loss), _f32(work), _stream(stream)))
     return g, loss
+
+
+def hifde_mlp_grad_noalloc(params, feat, target, grad, loss, stream=None):
+    """As :func:`hifde_mlp_grad` into the caller's ``grad`` (HIFDE_RANK_PARAMS
+    floats) and ``loss`` (one float), with the library's static workspace:
+    the call allocates no device memory."""
+    B = feat.shape[0]
+    check(lib().hifde_mlp_grad_noalloc(_f32(params, (HIFDE_RANK_PARAMS,)), B,
+                                       _f32(feat, (B, HIFDE_RANK_FEATURES)), _f32(target, (B,)),
+                                       _f32(grad, (HIFDE_RANK_PARAMS,)), _f32(loss, (1,)),
+                                       _stream(stream)))
 
 
 def hifde_mlp_adam(params, grad, m, v, step: int, lr: float, stream=None):

@@ -30,12 +30,13 @@ EXPORTED = [
     "hifde_build_tree", "hifde_factor", "hifde_solve", "hifde_pcg", "hifde_matvec",
     "hifde_stats", "hifde_export_sets", "hifde_plan_replay", "hifde_profile",
     "hifde_profile_read", "hifde_mlp_workspace", "hifde_mlp_forward", "hifde_mlp_grad",
-    "hifde_mlp_adam", "hifde_rank_features", "hifde_set_rank_model", "hifde_tree_free",
+    "hifde_mlp_grad_noalloc", "hifde_mlp_adam", "hifde_rank_features", "hifde_set_rank_model", "hifde_tree_free",
     "hifde_factor_free", "hifde_last_error",
 ]
 
 HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN = 16, 64
 HIFDE_RANK_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
+HIFDE_MLP_NOALLOC_MAX_BATCH = 8192
 
 HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP = 0, 1, 2, 3
 HIFDE_PROF_SWEEP_UP_WHOLE, HIFDE_PROF_SWEEP_DOWN_WHOLE = 4, 5
@@ -117,6 +118,7 @@ def lib():
     L.hifde_mlp_workspace.argtypes = [i64, C.POINTER(C.c_int64)]
     L.hifde_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
     L.hifde_mlp_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.hifde_mlp_grad_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.hifde_mlp_adam.argtypes = [vp, vp, vp, vp, i64, C.c_float, vp]
     L.hifde_rank_features.argtypes = [vp, i32, vp, vp, i64, C.POINTER(C.c_int64), vp]
     L.hifde_set_rank_model.argtypes = [vp, vp, i64]

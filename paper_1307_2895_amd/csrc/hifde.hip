@@ -2618,26 +2618,76 @@ int hifde_mlp_forward(const float* params, int64_t nbatch, const float* feat, fl
   });
 }
 
+// The four launches of one gradient: forward with the activations kept,
+// backward through them, the parameter gradient and the loss.  work holds
+// y, dy (nbatch each) and h1, h2, dz1, dz2 (nbatch x kRankH each); every
+// launch writes its part of it for all nbatch samples before any reads it.
+static void mlp_grad_launch(const float* params, int64_t nbatch, const float* feat,
+                            const float* target, float* grad, float* loss, float* work,
+                            hipStream_t st) {
+  float* y = work;
+  float* dy = y + nbatch;
+  float* h1 = dy + nbatch;
+  float* h2 = h1 + nbatch * kRankH;
+  float* dz1 = h2 + nbatch * kRankH;
+  float* dz2 = dz1 + nbatch * kRankH;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
+                     feat, y, h1, h2);
+  hipLaunchKernelGGL(k_mlp_backprop, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
+                     y, target, h1, h2, dy, dz1, dz2);
+  hipLaunchKernelGGL(k_mlp_param_grad, dim3(nblk(kRankP)), dim3(kThreads), 0, st, nbatch, feat,
+                     h1, h2, dy, dz1, dz2, grad);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(kThreads), 0, st, nbatch, y, target, loss);
+  HIP_CHECK(hipGetLastError());
+}
+
 int hifde_mlp_grad(const float* params, int64_t nbatch, const float* feat, const float* target,
                    float* grad, float* loss, void* work, void* hip_stream) {
   if (!params || !feat || !target || !grad || !loss || !work || nbatch < 1)
     return fail(HIFDE_EINVAL, "bad arguments");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   return guarded([&] {
-    float* y = static_cast<float*>(work);
-    float* dy = y + nbatch;
-    float* h1 = dy + nbatch;
-    float* h2 = h1 + nbatch * kRankH;
-    float* dz1 = h2 + nbatch * kRankH;
-    float* dz2 = dz1 + nbatch * kRankH;
-    hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
-                       feat, y, h1, h2);
-    hipLaunchKernelGGL(k_mlp_backprop, dim3(nblk(nbatch)), dim3(kThreads), 0, st, params, nbatch,
-                       y, target, h1, h2, dy, dz1, dz2);
-    hipLaunchKernelGGL(k_mlp_param_grad, dim3(nblk(kRankP)), dim3(kThreads), 0, st, nbatch, feat,
-                       h1, h2, dy, dz1, dz2, grad);
-    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(kThreads), 0, st, nbatch, y, target, loss);
-    HIP_CHECK(hipGetLastError());
+    mlp_grad_launch(params, nbatch, feat, target, grad, loss, static_cast<float*>(work), st);
+  });
+}
+
+// Workspace of hifde_mlp_grad_noalloc: the activations and their gradients
+// of up to HIFDE_MLP_NOALLOC_MAX_BATCH samples.  Each device holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name in
+// host code is not a device address).
+constexpr int64_t kMlpStaticBatch = HIFDE_MLP_NOALLOC_MAX_BATCH;
+static __device__ __align__(256) float mlp_scratch[(4 * kRankH + 2) * kMlpStaticBatch];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_mlp_scratch_mu;
+static float* g_mlp_scratch[kMaxDevices] = {};
+
+// Device address of mlp_scratch on the current device, looked up on the
+// first call on that device and kept.
+static float* mlp_scratch_address() {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(HIFDE_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_mlp_scratch_mu);
+  if (!g_mlp_scratch[dev]) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(mlp_scratch)));
+    if (!p) throw Error(HIFDE_EDEVICE, "no device address for the static workspace");
+    g_mlp_scratch[dev] = static_cast<float*>(p);
+  }
+  return g_mlp_scratch[dev];
+}
+
+int hifde_mlp_grad_noalloc(const float* params, int64_t nbatch, const float* feat,
+                           const float* target, float* grad, float* loss, void* hip_stream) {
+  if (!params || !feat || !target || !grad || !loss || nbatch < 1)
+    return fail(HIFDE_EINVAL, "bad arguments");
+  if (nbatch > kMlpStaticBatch)
+    return fail(HIFDE_EINVAL, "nbatch exceeds HIFDE_MLP_NOALLOC_MAX_BATCH");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return guarded([&] {
+    mlp_grad_launch(params, nbatch, feat, target, grad, loss, mlp_scratch_address(), st);
   });
 }
 
