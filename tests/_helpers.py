@@ -54,6 +54,30 @@ def compare_sets(OF, F, check_skeletons=True):
     return cm, gm, sm, first
 
 
+def compare_structure(OF, F, levels):
+    """Cells (p, c^N) of levels < ``levels`` and groups (c, c^N) of levels
+    l + 1/2 < ``levels``: the sets that no skeleton choice of those levels
+    changes.  Returns (cell mismatches, group mismatches)."""
+    import paper_1307_2895_amd as H
+    sets, _ = OH.export_sets(OF)
+    cm = gm = 0
+    for l in range(levels):
+        lev = sets[l]
+        gc = H.hifde_export_sets(F, 2 * l)
+        if len(gc) != len(lev["cells"]):
+            return 10 ** 9, 0
+        for (cid, p, q), (hid, hl) in zip(lev["cells"], gc):
+            if cid != hid or not np.array_equal(p, hl[0]) or not np.array_equal(q, hl[1]):
+                cm += 1
+        gg = H.hifde_export_sets(F, 2 * l + 1)
+        if len(gg) != len(lev["groups"]):
+            return cm, 10 ** 9
+        for (gid, c, cN, _, _), (hid, hl) in zip(lev["groups"], gg):
+            if gid != hid or not np.array_equal(c, hl[0]) or not np.array_equal(cN, hl[1]):
+                gm += 1
+    return cm, gm
+
+
 def rel_residual(A, u, f):
     r = f - A @ u
     return np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=0)
