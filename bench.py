@@ -10,7 +10,9 @@ in HBM before the timed region starts.
 Prints one JSON line.  ``value`` is the whole-step throughput
 N * nrhs / (t_factor + t_pcg) in DOF*RHS/s; the factor DOF/s and solve
 DOF*RHS/s components, the plain FP64 path, the roofline of the dominant
-kernel and the CPU oracle baseline are reported beside it.
+kernel (HBM) and of the factorization (matrix cores, with the FP64 top
+block), the 3D workloads (one step each) and the CPU oracle baseline are
+reported beside it.
 """
 from __future__ import annotations
 
@@ -25,18 +27,35 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from synth import workloads as W  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 # The kernel the roofline object describes: the upward sweep of F^-1 over
-# the level-0 cells, both colors in one launch (k_sweep_up_c<float, float,
-# 1, true>, the 16-right-hand-side instance), the kernel with the most time
-# per step.  Its launches are exactly those of the profile class
-# HIFDE_PROF_SWEEP_UP_ONE.
-DOMINANT_KERNEL = "k_sweep_up_c<float, float, 1, true>"
+# the level-0 cells, both colors in one launch (k_sweep_up_c), the kernel
+# with the most time per step.  Its launches are exactly those of the
+# profile class HIFDE_PROF_SWEEP_UP_ONE.
 DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_solve.inc")
 CALIB_COPY_BYTES = 512 << 20
+# workloads timed beside the headline one (3D configurations; the last with
+# 256 and with 1 right-hand side on the same factorization)
+EXTRA_WORKLOADS = ("laplace3d_n64", "grf3d_n128")
+
+
+def dominant_kernel(mixed, nrhs):
+    """Template instance of k_sweep_up_c that a solve with nrhs right-hand
+    sides launches: element type, 16-column tiles per wavefront (1 up to 16
+    right-hand sides, 2 up to 32, else 4) and 16-byte vector access when
+    nrhs is a multiple of 16 bytes' worth of elements."""
+    t = "float" if mixed else "double"
+    nt = 1 if nrhs <= 16 else 2 if nrhs <= 32 else 4
+    vec = nrhs % (4 if mixed else 2) == 0
+    return f"k_sweep_up_c<{t}, {t}, {nt}, {'true' if vec else 'false'}>"
+
+
+DOMINANT_KERNEL = dominant_kernel(True, 16)   # the headline workload's instance
 
 
 def parse():
@@ -47,7 +66,12 @@ def parse():
     ap.add_argument("--workload", default="contrast2d_n1024")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path")
-    ap.add_argument("--cpu-n", type=int, default=256, help="grid side of the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=512,
+                    help="side of the sub-grid of the workload's own inputs the CPU oracle runs on")
+    ap.add_argument("--cpu-nrhs", type=int, default=4,
+                    help="right-hand sides (the workload's first columns) of the CPU sample")
+    ap.add_argument("--no-extra", action="store_true",
+                    help=f"skip the extra workloads {', '.join(EXTRA_WORKLOADS)}")
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"first run one plain device copy of {CALIB_COPY_BYTES >> 20} MiB "
                          "(scale reference for HBM counters)")
@@ -143,32 +167,172 @@ def pmc_summary(fetch_dir, write_dir, workload):
     return "\n".join(lines)
 
 
-def cpu_baseline(w, n_sample, nrhs):
-    """The oracle, untouched, on a bounded sample of the same workload recipe:
-    same field recipe, leaf, eps and right-hand-side distribution on an
-    n_sample^dim grid; factor + PCG (FP64, tol 1e-12) on nrhs columns."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _subgrid(w, a, f, ns):
+    """The workload's own link coefficients and right-hand sides restricted
+    to the sub-grid x_k < ns (Dirichlet data outside it): links 0..ns along
+    each axis k, the first ns unknowns along the others."""
+    d = w.dim
+    sub = []
+    for k in range(d):
+        sl = []
+        for pos in range(d):
+            axis = d - 1 - pos          # C-order position -> grid axis
+            sl.append(slice(0, ns + 1) if axis == k else slice(0, ns))
+        sub.append(np.ascontiguousarray(a[k][tuple(sl)]))
+    grid = f.reshape((w.n,) * d + (f.shape[1],), order="F")
+    fs = grid[(slice(0, ns),) * d].reshape(ns ** d, f.shape[1], order="F")
+    return sub, np.asfortranarray(fs)
+
+
+def _oracle_run(w, a, f, ns):
     from oracle import hifde as OH
     from oracle import pcg as OP
-    from synth import workloads as W
-    a = W.make_field(w.dim, n_sample, w.field, w.seed_a)
-    f = W.make_rhs(n_sample ** w.dim, nrhs, w.seed_f)
     t0 = time.perf_counter()
-    F = OH.factor(w.dim, n_sample, w.leaf, a, eps=w.eps)
+    F = OH.factor(w.dim, ns, w.leaf, a, eps=w.eps)
     t1 = time.perf_counter()
-    _, its, rr = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 200)
+    _, its, _ = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 200)
     t2 = time.perf_counter()
+    return t1 - t0, t2 - t1, int(np.max(its))
+
+
+def cpu_baseline(w, a_full, f_full, n_sample, nrhs):
+    """The oracle, untouched, on a bounded sample of the workload's own
+    inputs: the n_sample^dim sub-grid of its coefficient field and the first
+    nrhs right-hand sides restricted to it, same leaf, eps and tolerance;
+    factor + PCG (FP64, tol 1e-12).  The whole grid would take the oracle
+    minutes; the sample keeps it to tens of seconds.  A second run with one
+    BLAS thread on the n_sample/2 sub-grid gives the single-core figure."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    a, f = _subgrid(w, a_full, f_full[:, :nrhs], n_sample)
+    tf, tp, it = _oracle_run(w, a, f, n_sample)
     Ns = n_sample ** w.dim
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    ns1 = max(w.leaf * 2, n_sample // 2)
+    a1, f1 = _subgrid(w, a_full, f_full[:, :nrhs], ns1)
+    with threadpool_limits(limits=1):
+        tf1, tp1, it1 = _oracle_run(w, a1, f1, ns1)
+    N1 = ns1 ** w.dim
     return {
-        "value": Ns * nrhs / (t2 - t0),
+        "value": Ns * nrhs / (tf + tp),
         "unit": "DOF*RHS/s",
-        "cores": cores,
+        "cores": blas,
         "kind": "oracle",
-        "sample": (f"{w.field} field, {w.dim}D n={n_sample} (N={Ns}), leaf {w.leaf}, eps {w.eps}, "
-                   f"{nrhs} RHS; FP64 factor {t1 - t0:.2f} s + PCG to 1e-12 {t2 - t1:.2f} s "
-                   f"(iters {int(np.max(its))})"),
-        "factor_dof_per_s": Ns / (t1 - t0),
-        "solve_dof_rhs_per_s": Ns * nrhs / (t2 - t1),
+        "sample": (f"sub-grid {n_sample}^{w.dim} (N={Ns}) of the {w.name} inputs (its field and "
+                   f"its first {nrhs} right-hand sides), leaf {w.leaf}, eps {w.eps}: FP64 factor "
+                   f"{tf:.2f} s + PCG to 1e-12 {tp:.2f} s (iters {it}); Python with {blas} "
+                   f"BLAS threads"),
+        "cpu_model": _cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "factor_dof_per_s": Ns / tf,
+        "solve_dof_rhs_per_s": Ns * nrhs / tp,
+        "one_thread": {
+            "value": N1 * nrhs / (tf1 + tp1), "cores": 1,
+            "sample": f"sub-grid {ns1}^{w.dim} (N={N1}), {nrhs} RHS: factor {tf1:.2f} s + "
+                      f"PCG {tp1:.2f} s (iters {it1})",
+        },
+    }
+
+
+def run_workload(H, torch, w, prec, nrhs_list, steps, warmup, profile_sweep):
+    """Factor + PCG steps of one workload.  The first warmup step autotunes
+    the launch variants of every size bucket (the tree keeps the choices);
+    each timed step factors and then runs PCG for every right-hand-side
+    count in nrhs_list on that factorization.  Returns per-step timings,
+    statistics and the live HIP-event timing of the dominant sweep kernel
+    for the first right-hand-side count."""
+    N = w.N
+    dev = torch.device("cuda:0")
+    a_d = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in W.make_coefficients(w)]
+    f_d = {k: torch.from_numpy(W.make_rhs(N, k, w.seed_f)).to(dev) for k in nrhs_list}
+    tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
+    prof = {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0}
+
+    def step(profile=False, tune=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = H.hifde_factor(tree, a_d, None, w.eps, prec, flags=H.HIFDE_AUTOTUNE if tune else 0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = {"factor_s": t1 - t0, "stats": H.hifde_stats(F), "pcg": {}}
+        for i, k in enumerate(nrhs_list):
+            if profile and i == 0:
+                H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP_ONE, -1)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            u, its, rel = H.hifde_pcg(F, f_d[k], tol=1e-12, maxit=200)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if profile and i == 0:
+                H.hifde_profile(F, 0, -1)
+                r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP_ONE)
+                for key in prof:
+                    prof[key] += r[key]
+            res["pcg"][k] = (t3 - t2, its, rel)
+            del u
+        F.free()
+        return res
+
+    for i in range(warmup):
+        step(tune=(i == 0))
+        print(f"{w.name}: warmup step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    out = []
+    t_begin = time.perf_counter()
+    for k in range(steps):
+        r = step(profile=profile_sweep)
+        out.append(r)
+        pc = ", ".join(f"pcg[{n}] {1e3 * v[0]:.1f} ms ({int(v[1].max())} it)"
+                       for n, v in r["pcg"].items())
+        print(f"{w.name} step {k}: factor {1e3 * r['factor_s']:.1f} ms, {pc}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_begin
+    return out, t_total, prof
+
+
+def factor_roofline(stats, t_factor, mixed):
+    """Algorithmic flops of the whole factorization over its time, against
+    the matrix cores' dense peak for the cells' and groups' type, and the
+    FP64 top block (|s_L|^3/3) over its device time against the FP64 peak."""
+    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    achieved = stats["factor_flops"] / t_factor / 1e12
+    top = stats["top_size"]
+    top_fl = top ** 3 / 3.0
+    top_s = stats["top_ms"] / 1e3
+    top_ach = top_fl / top_s / 1e12 if top_s > 0 else 0.0
+    return {
+        "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": None,
+        "flops": stats["factor_flops"], "factor_ms": 1e3 * t_factor,
+        "level_ms": [round(x, 3) for x in stats["level_ms"]],
+        "top_block": {"size": top, "flops": top_fl, "ms": stats["top_ms"],
+                      "achieved": top_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": top_ach / FP64_PEAK_TFLOPS},
+    }
+
+
+def sweep_roofline(prof, kernel, traffic):
+    nl = max(1, prof["launches"])
+    avg_s = prof["ms"] / nl / 1e3
+    bytes_launch = prof["bytes"] / nl
+    achieved = bytes_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "kernel": kernel, "launches": prof["launches"],
+        "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
+        "mfma_tflops": prof["flops"] / nl / avg_s / 1e12 if avg_s > 0 else 0.0,
     }
 
 
@@ -184,22 +348,17 @@ def main():
         sys.exit(2)
     import torch
     import paper_1307_2895_amd as H
-    from synth import workloads as W
 
     w = W.workload(args.workload)
     N, nrhs = w.N, w.nrhs
-    a_h = W.make_coefficients(w)
-    f_h = W.make_rhs(N, nrhs, w.seed_f)
-    dev = torch.device("cuda:0")
-    a_d = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in a_h]
-    f_d = torch.from_numpy(f_h).to(dev)
-    tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
-    prec = H.HIFDE_MIXED if w.precision == "mixed" else H.HIFDE_FP64
+    mixed = w.precision == "mixed"
+    prec = H.HIFDE_MIXED if mixed else H.HIFDE_FP64
 
     if args.calib_copy:
         # two plain copies of known size: a runtime block copy (wide loads)
         # and an elementwise scale by 1 on 4-byte-misaligned views, which
         # runs with one 4-byte load and store per lane like the sweep kernels
+        dev = torch.device("cuda:0")
         src = torch.ones(CALIB_COPY_BYTES // 4 + 1, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst[:-1].copy_(src[:-1])
@@ -207,47 +366,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    prof = {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0}
-
-    def step(p, profile=False, tune=False):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        F = H.hifde_factor(tree, a_d, None, w.eps, p, flags=H.HIFDE_AUTOTUNE if tune else 0)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if profile:
-            H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP_ONE, -1)
-        u, its, rel = H.hifde_pcg(F, f_d, tol=1e-12, maxit=200)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        if profile:
-            r = H.hifde_profile_read(F, H.HIFDE_PROF_SWEEP_UP_ONE)
-            for k in prof:
-                prof[k] += r[k]
-        st = H.hifde_stats(F)
-        F.free()
-        return t1 - t0, t2 - t1, its, rel, st
-
-    # warmup: the first step autotunes the launch variants of every size
-    # bucket; the tree keeps the choices for the timed steps
-    for i in range(args.warmup):
-        step(prec, tune=(i == 0))
-        print("warmup step done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    tf, tp, iters = [], [], None
-    t_begin = time.perf_counter()
-    for k in range(args.steps):
-        a, b, its, rel, st = step(prec, profile=True)
-        tf.append(a)
-        tp.append(b)
-        iters, relres, stats = its, rel, st
-        print(f"step {k}: factor {a*1e3:.1f} ms, pcg {b*1e3:.1f} ms, iters {int(its.max())}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_begin
+    runs, t_total, prof = run_workload(H, torch, w, prec, [nrhs], args.steps, args.warmup, True)
+    tf = [r["factor_s"] for r in runs]
+    tp = [r["pcg"][nrhs][0] for r in runs]
+    iters, relres, stats = runs[-1]["pcg"][nrhs][1], runs[-1]["pcg"][nrhs][2], runs[-1]["stats"]
     ms_step = 1e3 * t_total / args.steps
     t_f, t_p = float(np.median(tf)), float(np.median(tp))
-
+    kernel = dominant_kernel(mixed, nrhs)
     out = {
         "metric": "factor DOF/s + solve DOF*RHS/s, mixed vs FP64 GPU path at 1e-12 PCG residual",
         "value": N * nrhs / (t_total / args.steps),
@@ -259,7 +384,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 factor/F^-1, f64 PCG" if prec == H.HIFDE_MIXED else "f64",
+        "dtype": "f32 factor/F^-1, f64 PCG" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "dim": w.dim, "n": w.n, "N": N, "leaf": w.leaf,
                    "eps": w.eps, "field": w.field, "nrhs": nrhs, "tol": 1e-12},
@@ -275,29 +400,49 @@ def main():
             "factor_gflop": stats["factor_flops"] / 1e9,
         },
     }
-    nl = max(1, prof["launches"])
-    avg_s = prof["ms"] / nl / 1e3
-    bytes_launch = prof["bytes"] / nl
-    achieved = bytes_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-    traffic = read_traffic(w.name)
-    out["roofline"] = {
-        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-        "kernel": DOMINANT_KERNEL, "launches": prof["launches"],
-        "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
-        "mfma_tflops": prof["flops"] / nl / avg_s / 1e12 if avg_s > 0 else 0.0,
-    }
-    if not args.no_fp64 and prec == H.HIFDE_MIXED:
-        step(H.HIFDE_FP64, tune=True)        # tune the FP64 buckets (untimed)
-        a, b, its, rel, st = step(H.HIFDE_FP64)
+    out["roofline"] = sweep_roofline(prof, kernel,
+                                     read_traffic(w.name) if kernel == DOMINANT_KERNEL else None)
+    out["factor_roofline"] = factor_roofline(stats, t_f, mixed)
+    if not args.no_fp64 and mixed:
+        runs64, _, _ = run_workload(H, torch, w, H.HIFDE_FP64, [nrhs], 1, 1, False)
+        a = runs64[0]["factor_s"]
+        b, its, _ = runs64[0]["pcg"][nrhs]
         out["fp64_path"] = {
             "factor_dof_per_s": N / a, "solve_dof_rhs_per_s": N * nrhs / b,
             "factor_ms": 1e3 * a, "pcg_ms": 1e3 * b, "pcg_iters_max": int(np.max(its)),
             "step_dof_rhs_per_s": N * nrhs / (a + b),
+            "factor_roofline": factor_roofline(runs64[0]["stats"], a, False),
         }
         out["speedup_mixed_vs_fp64"] = (a + b) / (t_f + t_p)
+    if not args.no_extra:
+        extra = []
+        for name in EXTRA_WORKLOADS:
+            we = W.workload(name)
+            me = we.precision == "mixed"
+            counts = [we.nrhs, *we.extra_nrhs]
+            re_, _, pe = run_workload(H, torch, we, H.HIFDE_MIXED if me else H.HIFDE_FP64,
+                                      counts, 1, 1, True)
+            r = re_[0]
+            tfe = r["factor_s"]
+            item = {"workload": name, "dim": we.dim, "n": we.n, "N": we.N, "leaf": we.leaf,
+                    "eps": we.eps, "field": we.field, "precision": we.precision,
+                    "factor_ms": 1e3 * tfe, "factor_dof_per_s": we.N / tfe,
+                    "top_size": r["stats"]["top_size"],
+                    "factor_roofline": factor_roofline(r["stats"], tfe, me), "solves": []}
+            for k in counts:
+                t, its, rel = r["pcg"][k]
+                item["solves"].append({
+                    "nrhs": k, "pcg_ms": 1e3 * t, "pcg_iters_max": int(np.max(its)),
+                    "pcg_relres_max": float(np.max(rel)),
+                    "solve_dof_rhs_per_s": we.N * k / t,
+                    "step_dof_rhs_per_s": we.N * k / (tfe + t)})
+            item["roofline"] = sweep_roofline(pe, dominant_kernel(me, counts[0]), None)
+            extra.append(item)
+        out["extra_workloads"] = extra
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_n, nrhs)
+        a_h = W.make_coefficients(w)
+        f_h = W.make_rhs(N, nrhs, w.seed_f)
+        out["cpu_baseline"] = cpu_baseline(w, a_h, f_h, args.cpu_n, args.cpu_nrhs)
     print(json.dumps(out), flush=True)
 
 

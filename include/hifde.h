@@ -106,6 +106,12 @@ typedef struct {
   int64_t skel_panels;              /* 32-pivot panel sweeps launched for the
                                        skeleton fronts (all levels)          */
   int64_t tuned;                    /* size buckets the autotuner timed      */
+  double level_ms[HIFDE_MAX_LEVELS];  /* host wall time from the start of the
+                                       factorization to the end of level
+                                       l + 1/2 (the host has its ranks and
+                                       has queued the level's work)          */
+  double top_ms;                    /* device time of the top block (level L:
+                                       assembly, LDL^T in double, apply form) */
 } hifde_stats_t;
 
 /* Index sets of one (fractional) level, for comparison with other
@@ -134,6 +140,15 @@ typedef struct {
 int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels,
                      hifde_tree_t* out);
 
+/* Cap on the device memory the tree's factorizations and their solves may
+ * hold together (bytes; 0 removes the cap, the default).  It counts the
+ * blocks the tree's memory pool has taken from the device, including those
+ * kept for reuse after a factorization was freed (which are released first
+ * when the cap would be exceeded).  A call that would go over it fails with
+ * HIFDE_ENOMEM, frees what it took, and leaves the tree usable.  Host-only.
+ * EINVAL: NULL tree, bytes < 0. */
+int hifde_tree_set_memory_limit(hifde_tree_t tree, int64_t bytes);
+
 /* Factor A (Algorithm 4.1).  a[k] (k < dim) are DEVICE pointers to double
  * arrays of the link coefficients along axis k: n+1 links along axis k and n
  * along the others, x0 fastest (link j along axis k joins x_k = j-1 and
@@ -143,7 +158,11 @@ int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels,
  * reference to a or b.
  * EINVAL: eps outside [0, 1), NULL a[k], non-positive or non-finite a
  * (checked on the device), non-finite b.  ENOTSPD: a pivot of a diagonal
- * block was not positive; hifde_last_error() names the level and block. */
+ * block was not positive; hifde_last_error() names the level and block.
+ * The pivots of each level are read with that level's skeleton ranks, so
+ * the factorization stops at the level after the failing block (at the end
+ * when no level is skeletonized).  ENOMEM: the device, or the tree's cap
+ * (hifde_tree_set_memory_limit), ran out of memory. */
 int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b,
                  double eps, hifde_precision prec, uint32_t flags,
                  void* hip_stream, hifde_factor_t* out);
@@ -204,7 +223,10 @@ enum {
                                  x_s -= T x_r in the same launch            */
   HIFDE_PROF_SWEEP_UP_ONE = 8,   /* upward steps of the level-0 cells, both
                                     colors in one whole-front launch; the
-                                    x_q updates go to a contribution buffer */
+                                    x_q updates go to a contribution buffer.
+                                    Its bytes count the stored factor once
+                                    and every front's p and q vector rows
+                                    once per right-hand side              */
   HIFDE_PROF_CONTRIB_ADD = 9,    /* x_q -= the contributions of that launch,
                                     in color order                          */
   HIFDE_PROF_CLASSES = 10

@@ -16,7 +16,7 @@ from ._lib import (  # noqa: F401
     HIFDE_AUTOTUNE,
     HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES,
     HifdeError, Prof, Sets, Stats, check, lib,
-    HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE,
+    HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE, HIFDE_ENOMEM,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
     HIFDE_PROF_SWEEP_UP_WHOLE, HIFDE_PROF_SWEEP_DOWN_WHOLE, HIFDE_PROF_GROUP_UP,
     HIFDE_PROF_GROUP_DOWN, HIFDE_PROF_SWEEP_UP_ONE, HIFDE_PROF_CONTRIB_ADD,
@@ -79,6 +79,12 @@ def hifde_build_tree(dim: int, n: int, leaf: int, skip_levels: int = 0) -> Tree:
     h = C.c_void_p()
     check(lib().hifde_build_tree(dim, n, leaf, skip_levels, C.byref(h)))
     return Tree(h, dim, n, leaf, skip_levels)
+
+
+def hifde_tree_set_memory_limit(tree: Tree, nbytes: int):
+    """Cap (bytes, 0 = none) on the device memory the tree's factorizations
+    and solves may hold; exceeding it gives HIFDE_ENOMEM."""
+    check(lib().hifde_tree_set_memory_limit(tree._h, int(nbytes)))
 
 
 def hifde_factor(tree: Tree, a, b=None, eps: float = 1e-6, prec: int = HIFDE_FP64,
@@ -156,6 +162,7 @@ def hifde_stats(F: Factor) -> dict:
         "max_front": list(s.max_front[:L + 1]),
         "rank_groups": s.rank_groups, "rank_mae": s.rank_mae, "rebuckets": s.rebuckets,
         "skel_panels": s.skel_panels, "tuned": s.tuned,
+        "level_ms": list(s.level_ms[:L]), "top_ms": s.top_ms,
     }
 
 

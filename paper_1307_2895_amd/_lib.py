@@ -30,8 +30,8 @@ EXPORTED = [
     "hifde_build_tree", "hifde_factor", "hifde_solve", "hifde_pcg", "hifde_matvec",
     "hifde_stats", "hifde_export_sets", "hifde_plan_replay", "hifde_profile",
     "hifde_profile_read", "hifde_mlp_workspace", "hifde_mlp_forward", "hifde_mlp_grad",
-    "hifde_mlp_grad_noalloc", "hifde_mlp_adam", "hifde_rank_features", "hifde_set_rank_model", "hifde_tree_free",
-    "hifde_factor_free", "hifde_last_error",
+    "hifde_mlp_grad_noalloc", "hifde_mlp_adam", "hifde_rank_features", "hifde_set_rank_model",
+    "hifde_tree_set_memory_limit", "hifde_tree_free", "hifde_factor_free", "hifde_last_error",
 ]
 
 HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN = 16, 64
@@ -71,6 +71,8 @@ class Stats(C.Structure):
         ("rebuckets", C.c_int64),
         ("skel_panels", C.c_int64),
         ("tuned", C.c_int64),
+        ("level_ms", C.c_double * HIFDE_MAX_LEVELS),
+        ("top_ms", C.c_double),
     ]
 
 
@@ -124,6 +126,7 @@ def lib():
     L.hifde_set_rank_model.argtypes = [vp, vp, i64]
     L.hifde_profile_read.argtypes = [vp, i32, C.POINTER(Prof)]
     L.hifde_tree_free.argtypes = [vp]
+    L.hifde_tree_set_memory_limit.argtypes = [vp, i64]
     L.hifde_factor_free.argtypes = [vp]
     L.hifde_last_error.restype = C.c_char_p
     for name in EXPORTED:

@@ -83,6 +83,8 @@ struct DevMem {
 struct MemPool {
   std::mutex mu;
   std::multimap<size_t, void*> kept;
+  std::atomic<size_t> held{0};    // bytes obtained from hipMalloc, kept or in use
+  std::atomic<size_t> limit{0};   // cap on `held` (0: none)
   ~MemPool() { trim(); }
   void* take(size_t b, size_t* cap) {
     {
@@ -95,6 +97,14 @@ struct MemPool {
         return p;
       }
     }
+    const size_t lim = limit.load();
+    if (lim) {
+      if (held.load() + b > lim) trim();
+      if (held.load() + b > lim)
+        throw Error(HIFDE_ENOMEM, "device memory limit of the tree reached (" +
+                                      std::to_string(held.load() + b) + " > " +
+                                      std::to_string(lim) + " bytes)");
+    }
     void* p = nullptr;
     static const bool timing = getenv("HIFDE_TIMING") != nullptr;
     const auto t0 = std::chrono::steady_clock::now();
@@ -103,6 +113,7 @@ struct MemPool {
       trim();
       HIP_CHECK(hipMalloc(&p, b));
     }
+    held += b;
     if (timing)
       fprintf(stderr, "[hifde] pool miss: hipMalloc %zu bytes %.3f ms\n", b,
               std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
@@ -116,7 +127,10 @@ struct MemPool {
   }
   void trim() {
     std::lock_guard<std::mutex> g(mu);
-    for (auto& kv : kept) (void)hipFree(kv.second);
+    for (auto& kv : kept) {
+      (void)hipFree(kv.second);
+      held -= kv.first;
+    }
     kept.clear();
   }
 };
@@ -1194,12 +1208,8 @@ static void check_input(hifde_factor_s& F, hipStream_t st) {
   if (h & 2) throw Error(HIFDE_EINVAL, "b must be finite");
 }
 
-static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
-  if (n == 0) return;
-  std::vector<int> h(n);
-  HIP_CHECK(hipMemcpyAsync(h.data(), info, n * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipStreamSynchronize(st));
-  for (size_t i = 0; i < n; ++i)
+static void report_info(const std::vector<int>& h, const char* what, int l) {
+  for (size_t i = 0; i < h.size(); ++i)
     if (h[i] != 0) {
       char buf[200];
       snprintf(buf, sizeof buf, "non-positive pivot in %s %zu of level %d (panel at %d)", what, i, l,
@@ -1207,6 +1217,42 @@ static void check_info(const int* info, size_t n, const char* what, int l, hipSt
       throw Error(HIFDE_ENOTSPD, buf);
     }
 }
+
+static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
+  if (n == 0) return;
+  std::vector<int> h(n);
+  HIP_CHECK(hipMemcpyAsync(h.data(), info, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  report_info(h, what, l);
+}
+
+// Pivot flags of the level-l cells and of the level l-1/2 skeleton fronts,
+// queued for the host beside the level's ranks: a block that is not positive
+// definite stops the factorization at the first synchronization after it
+// rather than after every later level.
+struct LevelPivots {
+  std::vector<int> cells, groups;
+  void queue(const hifde_factor_s& F, int l, hipStream_t st) {
+    const CellLevel& C = F.cl[l];
+    if (C.info && C.st) {
+      cells.resize(C.st->fh.size());
+      if (!cells.empty())
+        HIP_CHECK(hipMemcpyAsync(cells.data(), C.info, cells.size() * sizeof(int),
+                                 hipMemcpyDeviceToHost, st));
+    }
+    if (l > 0 && F.gl[l - 1].info) {
+      const GroupLevel& G = F.gl[l - 1];
+      groups.resize(F.presize ? size_t(G.ngroup) : size_t(G.nskel));
+      if (!groups.empty())
+        HIP_CHECK(hipMemcpyAsync(groups.data(), G.info, groups.size() * sizeof(int),
+                                 hipMemcpyDeviceToHost, st));
+    }
+  }
+  void check(int l) const {   // after the stream has synchronized
+    report_info(cells, "cell", l);
+    report_info(groups, "group", l - 1);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Groups of level l+1/2: plan, base blocks, ID, skeleton fronts.
@@ -1610,9 +1656,12 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   // (copies to pageable memory return once the IDs are done)
   HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
+  LevelPivots piv;
+  piv.queue(F, l, st);
   HIP_CHECK(hipStreamSynchronize(st));
   tm.mark("  wait for IDs", l);
   check_input(F, st);
+  piv.check(l);
   // record skeletons; build the skeleton fronts
   int64_t fg_off = 0;
   G.gsel_h.clear();
@@ -1728,13 +1777,31 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
     P.adopt_level0(tree->l0);
   }
   tm.mark("level-0 plan", 0);
+  const auto t_start = std::chrono::steady_clock::now();
   for (int l = 0; l < L; ++l) {
     cells_level<T, T>(F, tree, l, st);
     tm.mark("cells", l);
     groups_level<T>(F, tree, l, st);
     tm.mark("groups", l);
+    if (l < HIFDE_MAX_LEVELS)
+      F.stats.level_ms[l] = std::chrono::duration<double, std::milli>(
+                                std::chrono::steady_clock::now() - t_start).count();
   }
+  // the top block is bracketed by timing events (read after the final
+  // synchronization below)
+  hipEvent_t top_ev[2] = {nullptr, nullptr};
+  if (!F.plan_only)
+    for (hipEvent_t& e : top_ev) HIP_CHECK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{top_ev};
+  if (top_ev[0]) HIP_CHECK(hipEventRecord(top_ev[0], st));
   cells_level<double, T>(F, tree, L, st);
+  if (top_ev[1]) HIP_CHECK(hipEventRecord(top_ev[1], st));
   F.flush_side(st);
   tm.mark("top", L);
   if (tm.on) {
@@ -1753,6 +1820,12 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
     }
   }
   tm.mark("pivot checks", L);
+  if (top_ev[1]) {
+    HIP_CHECK(hipEventSynchronize(top_ev[1]));
+    float ms = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&ms, top_ev[0], top_ev[1]));
+    F.stats.top_ms = ms;
+  }
 }
 
 static void fill_stats(hifde_factor_s& F) {
@@ -2006,9 +2079,11 @@ static bool sweep_up_one(hifde_factor_s& F, int level, const SweepSet& S, const 
   const size_t esz = sizeof(T), xsz = sizeof(TX);
   Work w{0, 0};
   if (F.prof_mask) {
+    // the stored factor read once and each front's p and q vector rows once
+    // per right-hand side (one upward pass of the level-0 cells)
     const double fac = S.fac[0] + S.fac[1], pr = S.prows[0] + S.prows[1];
     const double qr = double(S.cq_rows);
-    w = {fac * esz + pr * 4 + (2 * pr * xsz + qr * esz) * nrhs, 2.0 * nrhs * fac};
+    w = {fac * esz + (pr + qr) * xsz * nrhs, 2.0 * nrhs * fac};
   }
   const T* P = static_cast<const T*>(pk);
   const T* Dv = static_cast<const T*>(dinv);
@@ -2474,6 +2549,13 @@ int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels, hifde_tr
 }
 
 void hifde_tree_free(hifde_tree_t tree) { delete tree; }
+
+int hifde_tree_set_memory_limit(hifde_tree_t tree, int64_t bytes) {
+  if (!tree) return fail(HIFDE_EINVAL, "NULL tree");
+  if (bytes < 0) return fail(HIFDE_EINVAL, "bytes must be >= 0");
+  tree->pool->limit = size_t(bytes);
+  return HIFDE_OK;
+}
 
 void hifde_factor_free(hifde_factor_t F) {
   if (!F) return;

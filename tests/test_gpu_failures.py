@@ -1,0 +1,96 @@
+"""Failure paths of the C ABI on the GPU: a matrix that is not positive
+definite (ENOTSPD, naming the level of the failing block), PCG that misses
+its tolerance (ENOCONV with iters, relres and the last iterate filled), and
+a device-memory cap (ENOMEM).  After each failure the tree still factors a
+valid problem.  Every failure is forced by the inputs or the host: no kernel
+faults or hangs."""
+import numpy as np
+import pytest
+
+from oracle import hifde as OH
+from synth import workloads as W
+
+from _helpers import oracle_factor, torch_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _tree_still_works(T, a, f):
+    import paper_1307_2895_amd as H
+    F = H.hifde_factor(T, torch_inputs(a), None, 1e-6, H.HIFDE_MIXED)
+    _, its, rel = H.hifde_pcg(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=100)
+    assert np.all(rel <= 1.5e-12), rel
+    F.free()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("bval,level", [(-2000.0, 0), (-100.0, 2)])
+def test_not_positive_definite(prec, bval, level):
+    """b = -2000 makes the first level-0 interior block indefinite; b = -100
+    keeps the level-0 and level-1 blocks positive definite but not A
+    (smallest eigenvalue -80): the oracle (whose factorization counts 64
+    level-0 cells, 16 level-1 cells and the skeletonized level-3/2 edges
+    before its failing elimination) and the library both fail on the first
+    level-2 cell."""
+    import paper_1307_2895_amd as H
+    n, m = 64, 8
+    print(f"case b={bval} prec={prec}", flush=True)
+    a = W.make_field(2, n, "const", None)
+    b = np.full(n * n, bval)
+    with pytest.raises(OH.NotSPD):
+        OH.factor(2, n, m, a, b=b, eps=1e-6)
+    T = H.hifde_build_tree(2, n, m, 0)
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_factor(T, torch_inputs(a), torch.from_numpy(b).cuda(), 1e-6, prec)
+    assert ei.value.code == H.HIFDE_ENOTSPD
+    msg = str(ei.value)
+    print(msg)
+    assert f"cell" in msg and f"of level {level} " in msg, msg
+    _tree_still_works(T, a, W.make_rhs(n * n, 2, 5))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pcg_not_converged_fills_outputs(prec):
+    import paper_1307_2895_amd as H
+    n, m, eps = 64, 8, 1e-3
+    a = W.make_field(2, n, "bernoulli_contrast", 2)
+    OF = oracle_factor(2, n, m, a, 0.0)          # only its assembled A is used
+    T = H.hifde_build_tree(2, n, m, 0)
+    F = H.hifde_factor(T, torch_inputs(a), None, eps, prec)
+    f = W.make_rhs(n * n, 3, 6)
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_pcg(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=1)
+    assert ei.value.code == H.HIFDE_ENOCONV
+    u, its, rel = H.hifde_pcg(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=1,
+                              raise_on_noconv=False)
+    u = u.cpu().numpy()
+    assert np.all(its == 1), its
+    assert np.all(np.isfinite(u))
+    true_rel = np.linalg.norm(f - OF.A @ u, axis=0) / np.linalg.norm(f, axis=0)
+    print("relres", rel, "recomputed", true_rel)
+    assert np.all(rel > 1e-12) and np.all(rel < 1.0)
+    np.testing.assert_allclose(rel, true_rel, rtol=1e-8)
+    # one step of PCG from 0 is alpha F^-1 f with the exact line search
+    # alpha = f^T z / z^T A z
+    z = H.hifde_solve(F, torch.from_numpy(f).cuda()).cpu().numpy()
+    alpha = np.sum(f * z, axis=0) / np.sum(z * (OF.A @ z), axis=0)
+    np.testing.assert_allclose(u, z * alpha, rtol=1e-9, atol=1e-12 * np.abs(u).max())
+
+
+def test_memory_limit_gives_enomem_and_tree_recovers():
+    import paper_1307_2895_amd as H
+    n, m = 64, 8
+    a = W.make_field(2, n, "bernoulli_contrast", 2)
+    T = H.hifde_build_tree(2, n, m, 0)
+    H.hifde_tree_set_memory_limit(T, 1 << 20)
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_factor(T, torch_inputs(a), None, 1e-6, H.HIFDE_MIXED)
+    assert ei.value.code == H.HIFDE_ENOMEM
+    assert "limit" in str(ei.value)
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_tree_set_memory_limit(T, -1)
+    assert ei.value.code == H.HIFDE_EINVAL
+    H.hifde_tree_set_memory_limit(T, 0)
+    _tree_still_works(T, a, W.make_rhs(n * n, 2, 5))
