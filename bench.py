@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path")
     ap.add_argument("--cpu-n", type=int, default=512,
                     help="side of the sub-grid of the workload's own inputs the CPU oracle runs on")
-    ap.add_argument("--cpu-nrhs", type=int, default=4,
+    ap.add_argument("--cpu-nrhs", type=int, default=16,
                     help="right-hand sides (the workload's first columns) of the CPU sample")
     ap.add_argument("--no-extra", action="store_true",
                     help=f"skip the extra workloads {', '.join(EXTRA_WORKLOADS)}")
@@ -212,14 +212,15 @@ def cpu_baseline(w, a_full, f_full, n_sample, nrhs):
     nrhs right-hand sides restricted to it, same leaf, eps and tolerance;
     factor + PCG (FP64, tol 1e-12).  The whole grid would take the oracle
     minutes; the sample keeps it to tens of seconds.  A second run with one
-    BLAS thread on the n_sample/2 sub-grid gives the single-core figure."""
+    BLAS thread on the same sub-grid and two right-hand sides gives the
+    single-core figure."""
     from threadpoolctl import threadpool_info, threadpool_limits
     a, f = _subgrid(w, a_full, f_full[:, :nrhs], n_sample)
     tf, tp, it = _oracle_run(w, a, f, n_sample)
     Ns = n_sample ** w.dim
     blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    ns1 = max(w.leaf * 2, n_sample // 2)
-    a1, f1 = _subgrid(w, a_full, f_full[:, :nrhs], ns1)
+    ns1, nrhs1 = n_sample, min(nrhs, 2)
+    a1, f1 = a, f[:, :nrhs1]
     with threadpool_limits(limits=1):
         tf1, tp1, it1 = _oracle_run(w, a1, f1, ns1)
     N1 = ns1 ** w.dim
@@ -237,9 +238,10 @@ def cpu_baseline(w, a_full, f_full, n_sample, nrhs):
         "factor_dof_per_s": Ns / tf,
         "solve_dof_rhs_per_s": Ns * nrhs / tp,
         "one_thread": {
-            "value": N1 * nrhs / (tf1 + tp1), "cores": 1,
-            "sample": f"sub-grid {ns1}^{w.dim} (N={N1}), {nrhs} RHS: factor {tf1:.2f} s + "
+            "value": N1 * nrhs1 / (tf1 + tp1), "cores": 1,
+            "sample": f"sub-grid {ns1}^{w.dim} (N={N1}), {nrhs1} RHS: factor {tf1:.2f} s + "
                       f"PCG {tp1:.2f} s (iters {it1})",
+            "factor_dof_per_s": N1 / tf1,
         },
     }
 
@@ -351,8 +353,8 @@ def main():
 
     w = W.workload(args.workload)
     N, nrhs = w.N, w.nrhs
-    mixed = w.precision == "mixed"
-    prec = H.HIFDE_MIXED if mixed else H.HIFDE_FP64
+    prec = H.PRECISIONS[w.precision]
+    mixed = prec != H.HIFDE_FP64
 
     if args.calib_copy:
         # two plain copies of known size: a runtime block copy (wide loads)
@@ -384,10 +386,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 factor/F^-1, f64 PCG" if mixed else "f64",
+        "dtype": {H.HIFDE_MIXED: "f32 factor/F^-1, f64 PCG",
+                  H.HIFDE_MIXED_ELIM64: "f64 cell eliminations, f32 IDs/skeletonization/F^-1, "
+                                        "f64 top block and PCG",
+                  H.HIFDE_FP64: "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": w.name, "dim": w.dim, "n": w.n, "N": N, "leaf": w.leaf,
-                   "eps": w.eps, "field": w.field, "nrhs": nrhs, "tol": 1e-12},
+                   "eps": w.eps, "field": w.field, "nrhs": nrhs, "tol": 1e-12,
+                   "precision": w.precision},
         "components": {
             "factor_dof_per_s": N / t_f,
             "solve_dof_rhs_per_s": N * nrhs / t_p,
@@ -403,6 +409,15 @@ def main():
     out["roofline"] = sweep_roofline(prof, kernel,
                                      read_traffic(w.name) if kernel == DOMINANT_KERNEL else None)
     out["factor_roofline"] = factor_roofline(stats, t_f, mixed)
+    if not args.no_fp64 and prec == H.HIFDE_MIXED_ELIM64:
+        # the all-float factorization, for comparison
+        r32, _, _ = run_workload(H, torch, w, H.HIFDE_MIXED, [nrhs], 1, 1, False)
+        a = r32[0]["factor_s"]
+        b, its, _ = r32[0]["pcg"][nrhs]
+        out["mixed_f32_path"] = {
+            "factor_ms": 1e3 * a, "pcg_ms": 1e3 * b, "pcg_iters_max": int(np.max(its)),
+            "step_dof_rhs_per_s": N * nrhs / (a + b),
+        }
     if not args.no_fp64 and mixed:
         runs64, _, _ = run_workload(H, torch, w, H.HIFDE_FP64, [nrhs], 1, 1, False)
         a = runs64[0]["factor_s"]
@@ -418,10 +433,10 @@ def main():
         extra = []
         for name in EXTRA_WORKLOADS:
             we = W.workload(name)
-            me = we.precision == "mixed"
+            pe_ = H.PRECISIONS[we.precision]
+            me = pe_ != H.HIFDE_FP64
             counts = [we.nrhs, *we.extra_nrhs]
-            re_, _, pe = run_workload(H, torch, we, H.HIFDE_MIXED if me else H.HIFDE_FP64,
-                                      counts, 1, 1, True)
+            re_, _, pe = run_workload(H, torch, we, pe_, counts, 1, 1, True)
             r = re_[0]
             tfe = r["factor_s"]
             item = {"workload": name, "dim": we.dim, "n": we.n, "N": we.N, "leaf": we.leaf,

@@ -53,8 +53,14 @@ typedef enum {
 
 typedef enum {
   HIFDE_FP64 = 0,      /* every step in double precision                    */
-  HIFDE_MIXED = 1      /* cell/group steps and F^-1 in float; the top block
+  HIFDE_MIXED = 1,     /* cell/group steps and F^-1 in float; the top block
                           factorization, residuals and PCG in double         */
+  HIFDE_MIXED_ELIM64 = 2 /* as HIFDE_MIXED, but the cell eliminations of
+                          Lemma 2.1 (LDL^T, W and the Schur update of each
+                          front) run in double; their apply form is rounded
+                          to float for the sweeps.  For strongly varying
+                          coefficients, where float Schur complements lose
+                          the small differences of large terms            */
 } hifde_precision;
 
 enum {

@@ -12,7 +12,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (  # noqa: F401
-    HIFDE_FP64, HIFDE_MIXED, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH, HIFDE_USE_RANK_MODEL,
+    HIFDE_FP64, HIFDE_MIXED, HIFDE_MIXED_ELIM64, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH, HIFDE_USE_RANK_MODEL,
     HIFDE_AUTOTUNE,
     HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES,
     HifdeError, Prof, Sets, Stats, check, lib,
@@ -23,6 +23,10 @@ from ._lib import (  # noqa: F401
     HIFDE_PROF_CLASSES, HIFDE_RANK_FEATURES, HIFDE_RANK_HIDDEN, HIFDE_RANK_PARAMS,
     HIFDE_MLP_NOALLOC_MAX_BATCH,
 )
+
+
+# Workload precision names -> hifde_precision.
+PRECISIONS = {"fp64": HIFDE_FP64, "mixed": HIFDE_MIXED, "mixed_elim64": HIFDE_MIXED_ELIM64}
 
 
 class Tree:

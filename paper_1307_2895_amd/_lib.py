@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhifde.so")
 
 HIFDE_OK, HIFDE_EINVAL, HIFDE_ENOMEM, HIFDE_EDEVICE, HIFDE_ENOTSPD, HIFDE_ENOCONV, HIFDE_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
-HIFDE_FP64, HIFDE_MIXED = 0, 1
+HIFDE_FP64, HIFDE_MIXED, HIFDE_MIXED_ELIM64 = 0, 1, 2
 HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_AUTOTUNE, HIFDE_NO_GRAPH = 1, 4, 8, 16
 HIFDE_PRESIZE_WORST_CASE = 64
 HIFDE_SWEEP_ROW_TILES = 128

@@ -19,9 +19,12 @@ struct SrcDev {
   int64_t colmap;
 };
 
-// Base addresses of the pools the sources of one launch refer to.
+// Base addresses and element sizes (4: float, 8: double) of the pools the
+// sources of one launch refer to.  The pools of one level can differ in
+// type: cells eliminated in double beside float groups.
 struct PoolTable {
   const void* p[3];
+  int32_t esz[3];
 };
 enum : int32_t { POOL_CELLS = 0, POOL_BASE = 1, POOL_FG = 2 };
 

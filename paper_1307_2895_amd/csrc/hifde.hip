@@ -453,12 +453,14 @@ struct GroupStatic {
 struct CellLevel {
   std::shared_ptr<CellStatic> st;
   void* pool = nullptr;              // frontal matrices
+  int esz = 0;                       // their element size (4 or 8)
   int* info = nullptr;
   void *pk = nullptr, *pt = nullptr, *dinv = nullptr;  // packed apply form (up, down), D^-1
 };
 
 struct GroupLevel {
   std::shared_ptr<GroupStatic> st;
+  int esz = 0;                       // element size of base, gather, T and fronts
   std::vector<GroupDev> gh;          // with k, skel, fg_off, idx filled in
   GroupDev* groups = nullptr;
   void *base = nullptr, *gw = nullptr, *fg = nullptr, *tpool = nullptr;
@@ -935,24 +937,72 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
   HIP_CHECK(hipGetLastError());
 }
 
+// One column-block step of apply_form: the fronts still active, the row
+// tiles of the tallest, and how the finished columns are split over
+// work-groups.  A step whose launch would hold fewer work-groups than the
+// device has compute units (levels of few, large fronts: the top block, the
+// upper 3D levels) splits its finished columns into ranges of whole panels,
+// at most kInvSplitMax and at least four panels each.
+constexpr int kInvSplitMax = 16;
+struct InvStep {
+  int J = 0;
+  unsigned na = 0;
+  int64_t tiles = 0;
+  int nsplit = 1, kchunk = 0;
+};
+static std::vector<InvStep> inv_steps(const std::vector<FrontDev>& fh, bool bounds, bool sorted) {
+  std::vector<InvStep> out;
+  int pmax = 0;
+  for (const FrontDev& f : fh) pmax = std::max(pmax, f.p);
+  for (int J = ((pmax - 1) / kNB) * kNB; J >= 0 && pmax > 0; J -= kNB) {
+    InvStep s;
+    s.J = J;
+    int kblocks = 0;
+    for (const auto& f : fh) {
+      if (J >= f.p) continue;
+      const int nb = bounds ? 1 : std::min(kNB, f.p - J);
+      s.tiles = std::max<int64_t>(s.tiles, (f.s - J - nb + kIR - 1) / kIR);
+      kblocks = std::max(kblocks, (f.p - J - std::min(kNB, f.p - J) + kNB - 1) / kNB);
+    }
+    s.na = active_fronts(fh, J, sorted);
+    if (s.na == 0) continue;
+    const int64_t wgs = int64_t(s.na) * s.tiles;
+    if (s.tiles > 0 && wgs < 256 && kblocks >= 8) {
+      const int want = int(std::min<int64_t>(kInvSplitMax, (512 + wgs - 1) / wgs));
+      s.nsplit = std::max(1, std::min(want, kblocks / 4));
+      const int per = (kblocks + s.nsplit - 1) / s.nsplit;
+      s.kchunk = per * kNB;
+      s.nsplit = (kblocks + per - 1) / per;
+    }
+    out.push_back(s);
+  }
+  return out;
+}
+
 // Buffers of apply_form: the column block of B in flight, s x kNB per front,
-// and each front's offset in it.
+// each front's offset in it, and the partial residuals of split steps
+// (nsplit x s x kNB per front, at the front's offset times nsplit).
 template <typename T>
 struct InvWork {
   T* tmp = nullptr;
   const int64_t* toff = nullptr;
+  T* part = nullptr;
 };
 template <typename T>
-static InvWork<T> apply_form_work(Arena& mem, const std::vector<FrontDev>& fh, hipStream_t st) {
+static InvWork<T> apply_form_work(Arena& mem, const std::vector<FrontDev>& fh, hipStream_t st,
+                                  bool bounds = false, bool sorted = true) {
   std::vector<int64_t> toff(fh.size());
   int64_t tot = 0;
   for (size_t i = 0; i < fh.size(); ++i) {
     toff[i] = tot;
     tot += int64_t(fh[i].s) * kNB;
   }
+  int smax = 1;
+  for (const InvStep& s : inv_steps(fh, bounds, sorted)) smax = std::max(smax, s.nsplit);
   InvWork<T> w;
   w.tmp = mem.get<T>(size_t(std::max<int64_t>(tot, 1)));
   w.toff = mem.upload(toff, st);
+  if (smax > 1) w.part = mem.get<T>(size_t(tot) * size_t(smax));
   return w;
 }
 
@@ -964,60 +1014,73 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
                        const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
                        bool sorted = false, int variant = 1, const InvWork<T>* work = nullptr) {
   if (fh.empty()) return;
-  int pmax = 0;
-  for (const FrontDev& f : fh) pmax = std::max(pmax, f.p);
-  const InvWork<T> w = work ? *work : apply_form_work<T>(mem, fh, st);
+  const InvWork<T> w = work ? *work : apply_form_work<T>(mem, fh, st, bounds, sorted);
   T* tmp = w.tmp;
   const int64_t* toff_d = w.toff;
-  for (int J = ((pmax - 1) / kNB) * kNB; J >= 0 && pmax > 0; J -= kNB) {
-    int64_t tiles = 0;
-    for (const auto& f : fh) {
-      if (J >= f.p) continue;
-      const int nb = bounds ? 1 : std::min(kNB, f.p - J);
-      tiles = std::max<int64_t>(tiles, (f.s - J - nb + kIR - 1) / kIR);
-    }
-    const unsigned na = active_fronts(fh, J, sorted);
-    if (na == 0) continue;
+  int smax = 0;
+  for (const FrontDev& f : fh) smax = std::max(smax, f.s);
+  const unsigned chunks = unsigned(std::max(1, (smax + kCommitRows - 1) / kCommitRows));
+  for (const InvStep& s : inv_steps(fh, bounds, sorted)) {
+    const int J = s.J;
+    const unsigned na = s.na;
+    const int64_t tiles = s.tiles;
     if (tiles > 0) {
-      const unsigned g = front_tile_grid(na, tiles, "inversion grid");
-      if (variant == 1)
+      if (variant == 1 && s.nsplit > 1 && w.part) {
+        const unsigned g = front_tile_grid(na, tiles * s.nsplit, "inversion grid");
         hipLaunchKernelGGL(k_inv_step_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, J,
-                           tmp, toff_d, int(na), int(tiles));
-      else
+                           tmp, toff_d, int(na), int(tiles * s.nsplit), s.nsplit, s.kchunk,
+                           w.part);
+        hipLaunchKernelGGL(k_inv_finish<T>, dim3(front_tile_grid(na, tiles, "inversion grid")),
+                           dim3(kThreads), 0, st, pool, fronts_d, J, tmp, toff_d, int(na),
+                           int(tiles), s.nsplit, static_cast<const T*>(w.part));
+      } else if (variant == 1) {
+        const unsigned g = front_tile_grid(na, tiles, "inversion grid");
+        hipLaunchKernelGGL(k_inv_step_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, J,
+                           tmp, toff_d, int(na), int(tiles), 1, 0, static_cast<T*>(nullptr));
+      } else {
+        const unsigned g = front_tile_grid(na, tiles, "inversion grid");
         hipLaunchKernelGGL(k_inv_step<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
                            toff_d, int(na), int(tiles));
+      }
     }
-    hipLaunchKernelGGL(k_inv_commit<T>, dim3(na), dim3(kThreads), 0, st, pool, fronts_d, J, tmp,
-                       toff_d);
+    // rows of the fronts still below J: chunks past a front's end return
+    const unsigned ch = na < 64 ? chunks : 1u;
+    hipLaunchKernelGGL(k_inv_commit<T>, dim3(na, ch), dim3(kThreads), 0, st, pool, fronts_d, J,
+                       tmp, toff_d);
   }
   HIP_CHECK(hipGetLastError());
 }
 
 // Packed apply form and D^-1 of every front (the sweeps' copy).
-template <typename T>
+// TP: the sweeps' type (float under the mixed precisions, double for the top
+// block and in double precision).
+template <typename T, typename TP = T>
 static void pack_fronts(Arena& mem, const T* pool, const std::vector<FrontDev>& fh,
                         const FrontDev* fronts_d, const SweepSet& S, void** pk, void** pt,
                         void** dinv, hipStream_t st) {
-  *pk = mem.get<T>(size_t(std::max<int64_t>(S.pk_elems, 1)));
-  *pt = mem.get<T>(size_t(std::max<int64_t>(S.pt_elems, 1)));
-  *dinv = mem.get<T>(size_t(std::max<int64_t>(S.dv_elems, 1)));
+  *pk = mem.get<TP>(size_t(std::max<int64_t>(S.pk_elems, 1)));
+  *pt = mem.get<TP>(size_t(std::max<int64_t>(S.pt_elems, 1)));
+  *dinv = mem.get<TP>(size_t(std::max<int64_t>(S.dv_elems, 1)));
   if (fh.empty()) return;
   int smax = 0;
   for (const FrontDev& f : fh) smax = std::max(smax, f.s);
   const unsigned rtmax = unsigned((smax + 15) / 16);
   if (rtmax > 65535) throw Error(HIFDE_EINVAL, "front too large for the packing grid");
-  hipLaunchKernelGGL(k_pack<T>, dim3(unsigned(fh.size()), std::max(1u, rtmax)), dim3(kThreads), 0, st, pool, fronts_d,
-                     S.packs, static_cast<T*>(*pk), static_cast<T*>(*pt), static_cast<T*>(*dinv));
+  hipLaunchKernelGGL((k_pack<T, TP>), dim3(unsigned(fh.size()), std::max(1u, rtmax)), dim3(kThreads),
+                     0, st, pool, fronts_d, S.packs, static_cast<TP*>(*pk), static_cast<TP*>(*pt),
+                     static_cast<TP*>(*dinv));
   HIP_CHECK(hipGetLastError());
 }
 
 static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
-  PoolTable t{{nullptr, nullptr, nullptr}};
+  PoolTable t{{nullptr, nullptr, nullptr}, {0, 0, 0}};
   if (l_src < 0) return t;
   t.p[POOL_CELLS] = F.cl[l_src].pool;
+  t.esz[POOL_CELLS] = F.cl[l_src].esz;
   if (l_src < F.g.L) {
     t.p[POOL_BASE] = F.gl[l_src].base;
     t.p[POOL_FG] = F.gl[l_src].fg;
+    t.esz[POOL_BASE] = t.esz[POOL_FG] = F.gl[l_src].esz;
   }
   return t;
 }
@@ -1112,10 +1175,13 @@ static std::vector<FrontDev> sorted_by_p(const std::vector<FrontDev>& fh) {
   return out;
 }
 
-template <typename T, typename TS>
+// T: the type the cells are eliminated in; TP: the type of their packed
+// apply form (the sweeps' type).
+template <typename T, typename TP>
 static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_t st) {
   Planner& P = *F.planner;
   CellLevel& D = F.cl[l];
+  D.esz = int(sizeof(T));
   PhaseTimer tm;
   if (l == 0 && tree->c0) {
     F.join_skel();
@@ -1130,7 +1196,7 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
     tm.mark("  cell descriptors", l);
     if (l == 0) {
       tree->c0 = D.st;
-      tree->c0_esz = sizeof(T);
+      tree->c0_esz = sizeof(T);   // (the type its cells were first eliminated in)
     }
   }
   if (F.plan_only) return;
@@ -1154,7 +1220,7 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
       }
       for (const SrcDev& d : S.srcs_h) dmax = std::max(dmax, d.dim);
       for (int r = 0; r < rounds; ++r)
-        hipLaunchKernelGGL((k_assemble_round<T, TS>), dim3(S.ncell, (dmax + kAsmCols - 1) / kAsmCols),
+        hipLaunchKernelGGL((k_assemble_round<T>), dim3(S.ncell, (dmax + kAsmCols - 1) / kAsmCols),
                            dim3(kThreads), 0, st, static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps,
                            r, pt);
       if (tmax > 0)
@@ -1162,7 +1228,7 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
                            dim3(kThreads), 0, st, static_cast<T*>(D.pool), S.fronts, S.trips,
                            F.diag.as<double>(), F.offd.as<double>(), F.g.N);
     } else {
-      hipLaunchKernelGGL((k_assemble<T, TS>), dim3(S.ncell), dim3(kThreads), 0, st,
+      hipLaunchKernelGGL((k_assemble<T>), dim3(S.ncell), dim3(kThreads), 0, st,
                          static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps, S.trips,
                          F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt);
     }
@@ -1192,8 +1258,8 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
           apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v, &iw);
         });
     apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar, &iw);
-    pack_fronts<T>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
-                   &D.dinv, ss);
+    pack_fronts<T, TP>(F.mem, static_cast<const T*>(D.pool), S.fh, S.fronts, S.sw, &D.pk, &D.pt,
+                       &D.dinv, ss);
   };
 }
 
@@ -1423,6 +1489,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   Planner& P = *F.planner;
   const bool skel = F.eps > 0.0 && l >= F.g.skip;
   GroupLevel& G = F.gl[l];
+  G.esz = int(sizeof(T));
   PhaseTimer tm;
   P.plan_groups(l);
   tm.mark("  plan groups", l);
@@ -1445,7 +1512,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   HIP_CHECK(hipMemsetAsync(G.base, 0, size_t(S.base_elems) * sizeof(T), st));
   PoolTable pt_prev = pools_for_level(F, l - 1);
   if (G.ngroup > 0) {
-    hipLaunchKernelGGL((k_assemble<T, T>), dim3(G.ngroup), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((k_assemble<T>), dim3(G.ngroup), dim3(kThreads), 0, st,
                        static_cast<T*>(G.base), S.bfronts, S.bsrcs, S.maps, S.btrips,
                        F.diag.as<double>(), F.offd.as<double>(), F.g.N, pt_prev);
     HIP_CHECK(hipGetLastError());
@@ -1470,7 +1537,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       fg_all += int64_t(d.nc) * d.nc;
     }
   G.groups = F.mem.upload(G.gh, st);
-  PoolTable pt_cur{{F.cl[l].pool, nullptr, nullptr}};
+  PoolTable pt_cur{{F.cl[l].pool, nullptr, nullptr}, {F.cl[l].esz, 0, 0}};
   const int ncmax = S.ncmax;
   if (ncmax >= kCpqrWideFrom) {
     // large groups: source rounds, base block, loose links over column chunks
@@ -1755,7 +1822,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   }
 }
 
-template <typename T>
+// TC: the type of the cell eliminations below the top; T: the type of the
+// groups (IDs, skeletonization) and of the sweeps.  The top block is double.
+template <typename TC, typename T>
 static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   const int L = F.g.L;
   Planner& P = *F.planner;
@@ -1763,8 +1832,8 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   // the level-0 frontal matrices of a known tree are cleared first, so the
   // device does that while the host adopts the level-0 plan
   if (tree->l0 && tree->c0 && !F.plan_only) {
-    F.cl[0].pool = F.mem.get<T>(size_t(tree->c0->elems));
-    HIP_CHECK(hipMemsetAsync(F.cl[0].pool, 0, size_t(tree->c0->elems) * sizeof(T), st));
+    F.cl[0].pool = F.mem.get<TC>(size_t(tree->c0->elems));
+    HIP_CHECK(hipMemsetAsync(F.cl[0].pool, 0, size_t(tree->c0->elems) * sizeof(TC), st));
   }
   // Level 0 and its groups depend on the geometry only: plan once per tree.
   if (!tree->l0) {
@@ -1779,7 +1848,7 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   tm.mark("level-0 plan", 0);
   const auto t_start = std::chrono::steady_clock::now();
   for (int l = 0; l < L; ++l) {
-    cells_level<T, T>(F, tree, l, st);
+    cells_level<TC, T>(F, tree, l, st);
     tm.mark("cells", l);
     groups_level<T>(F, tree, l, st);
     tm.mark("groups", l);
@@ -1800,7 +1869,7 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
     }
   } ev_guard{top_ev};
   if (top_ev[0]) HIP_CHECK(hipEventRecord(top_ev[0], st));
-  cells_level<double, T>(F, tree, L, st);
+  cells_level<double, double>(F, tree, L, st);
   if (top_ev[1]) HIP_CHECK(hipEventRecord(top_ev[1], st));
   F.flush_side(st);
   tm.mark("top", L);
@@ -1828,6 +1897,10 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   }
 }
 
+// The sweeps (and the packed apply form of every front below the top) are
+// float under both mixed precisions.
+static bool float_sweeps(const hifde_factor_s& F) { return F.prec != HIFDE_FP64; }
+
 static void fill_stats(hifde_factor_s& F) {
   hifde_stats_t& s = F.stats;
   const Planner& P = *F.planner;
@@ -1836,7 +1909,7 @@ static void fill_stats(hifde_factor_s& F) {
   s.levels = F.g.L;
   double flops = 0.0, bytes = 0.0;
   int64_t mbytes = 0;
-  const size_t esz = F.prec == HIFDE_MIXED ? 4 : 8;
+  const size_t esz = float_sweeps(F) ? 4 : 8;
   for (int l = 0; l <= F.g.L && l < HIFDE_MAX_LEVELS; ++l) {
     const Level& lev = P.level(l);
     s.cells[l] = int64_t(lev.cells().size());
@@ -2469,8 +2542,9 @@ static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* co
       Planning() { planning_begin(); }
       ~Planning() { planning_end(); }
     } planning;
-    if (prec == HIFDE_MIXED) run_factor<float>(F, tree, st);
-    else run_factor<double>(F, tree, st);
+    if (prec == HIFDE_MIXED) run_factor<float, float>(F, tree, st);
+    else if (prec == HIFDE_MIXED_ELIM64) run_factor<double, float>(F, tree, st);
+    else run_factor<double, double>(F, tree, st);
   }
   F.join_side(st);
   HIP_CHECK(hipStreamSynchronize(st));
@@ -2511,7 +2585,7 @@ static void compare_factors(hifde_factor_s& A, hifde_factor_s& B, hipStream_t st
   };
   const int L = A.g.L;
   for (int l = 0; l <= L; ++l) {
-    const size_t esz = (l == L || A.prec == HIFDE_FP64) ? 8 : 4;
+    const size_t esz = (l == L || !float_sweeps(A)) ? 8 : 4;
     const SweepSet& S = A.cl[l].st->sw;
     same(A.cl[l].pk, B.cl[l].pk, size_t(S.pk_elems) * esz, "cell factors", l);
     same(A.cl[l].dinv, B.cl[l].dinv, size_t(S.dv_elems) * esz, "cell pivots", l);
@@ -2577,7 +2651,8 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
   *out = nullptr;
   if (!tree || !a) return fail(HIFDE_EINVAL, "tree or a is NULL");
   if (!(eps >= 0.0 && eps < 1.0)) return fail(HIFDE_EINVAL, "eps must lie in [0, 1)");
-  if (prec != HIFDE_FP64 && prec != HIFDE_MIXED) return fail(HIFDE_EINVAL, "unknown precision");
+  if (prec != HIFDE_FP64 && prec != HIFDE_MIXED && prec != HIFDE_MIXED_ELIM64)
+    return fail(HIFDE_EINVAL, "unknown precision");
   if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_AUTOTUNE |
                         HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE | HIFDE_SWEEP_ROW_TILES))
     return fail(HIFDE_EINVAL, "unknown flags");
@@ -2879,7 +2954,7 @@ int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, do
   return guarded([&] {
     const int64_t N = F->g.N, n = N * nrhs;
     ensure_X(*F, nrhs);
-    if (F->prec == HIFDE_MIXED) {
+    if (float_sweeps(*F)) {
       float* X = F->X.as<float>();
       hipLaunchKernelGGL(k_from_colmajor<float>, dim3(nblk(n)), dim3(kThreads), 0, st, N, int(nrhs),
                          f, ldf, X);
@@ -2930,7 +3005,7 @@ int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, doub
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   bool converged = true;
   int rc = guarded([&] {
-    if (F->prec == HIFDE_MIXED)
+    if (float_sweeps(*F))
       converged = run_pcg<float>(*F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
     else
       converged = run_pcg<double>(*F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);

@@ -61,7 +61,7 @@ WORKLOADS: Dict[str, Workload] = {
         "2D five-point Laplacian, N=4096, leaf 8x8"),
     "contrast2d_n1024": Workload(
         "contrast2d_n1024", 2, 1024, 16, 1e-6, "bernoulli_contrast", 16, 2, 20,
-        "mixed", "2D high-contrast (1e4) field, N=1048576, leaf 16x16"),
+        "mixed_elim64", "2D high-contrast (1e4) field, N=1048576, leaf 16x16"),
     "laplace3d_n64": Workload(
         "laplace3d_n64", 3, 64, 4, 1e-6, "const", 64, None, 30, "mixed",
         "3D seven-point Laplacian, N=262144, leaf 4^3"),

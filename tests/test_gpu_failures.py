@@ -25,7 +25,7 @@ def _tree_still_works(T, a, f):
     F.free()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("bval,level", [(-2000.0, 0), (-100.0, 2)])
 def test_not_positive_definite(prec, bval, level):
     """b = -2000 makes the first level-0 interior block indefinite; b = -100
@@ -51,7 +51,7 @@ def test_not_positive_definite(prec, bval, level):
     _tree_still_works(T, a, W.make_rhs(n * n, 2, 5))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_pcg_not_converged_fills_outputs(prec):
     import paper_1307_2895_amd as H
     n, m, eps = 64, 8, 1e-3

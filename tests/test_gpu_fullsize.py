@@ -88,7 +88,7 @@ def test_full_size(name, nrhs):
     print(f"case {name} nrhs={nrhs}", flush=True)
     a = W.make_coefficients(w)
     T = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
-    prec = H.HIFDE_MIXED if w.precision == "mixed" else H.HIFDE_FP64
+    prec = H.PRECISIONS[w.precision]
     F = H.hifde_factor(T, torch_inputs(a), None, w.eps, prec)
     _check_tree(F, w)
     f = W.make_rhs(w.N, nrhs, w.seed_f)
@@ -105,6 +105,6 @@ def test_full_size(name, nrhs):
     x = rng.standard_normal((w.N, 2))
     z = H.hifde_solve(F, torch.from_numpy(x).cuda()).cpu().numpy()
     xy, yx = x[:, 0] @ z[:, 1], x[:, 1] @ z[:, 0]
-    tol = 1e-4 if prec == H.HIFDE_MIXED else 1e-10
+    tol = 1e-4 if prec != H.HIFDE_FP64 else 1e-10
     assert abs(xy - yx) <= tol * np.sqrt(abs(x[:, 0] @ z[:, 0]) * abs(x[:, 1] @ z[:, 1]))
     assert x[:, 0] @ z[:, 0] > 0 and x[:, 1] @ z[:, 1] > 0

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("nrhs", [1, 16, 40])
 def test_graph_replays_match_direct_launches(prec, nrhs):
     import paper_1307_2895_amd as H
@@ -57,7 +57,7 @@ def test_graph_pcg_matches_direct():
     assert torch.equal(ug, ud)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_debug_determinism_flag(prec):
     import paper_1307_2895_amd as H
     dim, n, m = 3, 16, 4
@@ -76,7 +76,7 @@ def test_unknown_flags_rejected():
     assert ei.value.code == H.HIFDE_EINVAL
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("nrhs", [1, 16, 40])
 def test_whole_front_sweeps_match_row_tiles(prec, nrhs):
     """The whole-front sweeps (one work-group per front, interpolation fused
@@ -99,7 +99,7 @@ def test_whole_front_sweeps_match_row_tiles(prec, nrhs):
     assert torch.equal(uw, ur)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("what", ["a_negative", "a_nan", "b_inf"])
 def test_invalid_coefficients_rejected(prec, what):
     """Invalid coefficients are reported as HIFDE_EINVAL; the flags k_stencil
@@ -128,7 +128,7 @@ def test_invalid_coefficients_rejected(prec, what):
     assert H.hifde_stats(F)["top_size"] > 0
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_timed_first_sweep_with_graph_matches_unprofiled(prec):
     """Timing only the one-launch level-0 upward sweep runs that kernel
     directly and the rest of each F^-1 application from a graph captured

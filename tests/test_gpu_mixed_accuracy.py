@@ -6,7 +6,8 @@ Reported per case: the one-application relative residual
 iteration, Section 5) of both, and the PCG iteration counts.
 
 Bars.  The FP64 GPU path: within 2x of the oracle at the same eps.  The
-mixed path rounds every cell, group and ID step to float (unit roundoff
+mixed paths (HIFDE_MIXED, and HIFDE_MIXED_ELIM64 whose cell eliminations are
+double) round every cell or group and ID step to float (unit roundoff
 u = 6e-8); with the growth of the ID's triangular solve and of the Schur
 updates on these grids (about 100-200) that acts as a tolerance of about
 1e-5, so its one-application residual must stay within 2x of the oracle's
@@ -48,15 +49,16 @@ def _solver(F):
     return s
 
 
+@pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("dim,n,m,eps,field,seed", CASES)
-def test_mixed_one_application_residual(dim, n, m, eps, field, seed):
+def test_mixed_one_application_residual(dim, n, m, eps, field, seed, prec):
     import paper_1307_2895_amd as H
-    print(f"case dim={dim} n={n} leaf={m} eps={eps} field={field}", flush=True)
+    print(f"case dim={dim} n={n} leaf={m} eps={eps} field={field} prec={prec}", flush=True)
     a = W.make_field(dim, n, field, seed)
     OF = oracle_factor(dim, n, m, a, eps)
     N = n ** dim
     f = W.make_rhs(N, 4, 11)
-    _, Fm = gpu_factor(dim, n, m, a, eps, 1)
+    _, Fm = gpu_factor(dim, n, m, a, eps, prec)
     _, Fd = gpu_factor(dim, n, m, a, eps, 0)
     rm = rel_residual(OF.A, _solver(Fm)(f), f)
     rd = rel_residual(OF.A, _solver(Fd)(f), f)

@@ -83,16 +83,17 @@ def test_fp64_pcg_matches_oracle():
     assert np.all(np.abs(its - ito) <= 1)
 
 
+@pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("dim,n,m,eps,field,seed", [
     (2, 64, 8, 1e-6, "const", None),
     (2, 64, 8, 1e-6, "bernoulli_contrast", 2),
     (3, 16, 4, 1e-6, "const", None),
 ])
-def test_mixed_pcg_converges(dim, n, m, eps, field, seed):
+def test_mixed_pcg_converges(dim, n, m, eps, field, seed, prec):
     import paper_1307_2895_amd as H
     a = W.make_field(dim, n, field, seed)
     OF = oracle_factor(dim, n, m, a, eps)
-    T, F = gpu_factor(dim, n, m, a, eps, 1)
+    T, F = gpu_factor(dim, n, m, a, eps, prec)
     # the structural sets of level 0 and level 1/2 do not depend on any
     # skeleton choice: bit-exact in mixed precision too
     cm, gm = compare_structure(OF, F, levels=1)
@@ -111,7 +112,7 @@ def test_mixed_pcg_converges(dim, n, m, eps, field, seed):
 # Right-hand-side counts that change the PCG passes' 2D strips: 5 columns run
 # one column per lane (strips 51 unknowns wide, one per row of 48), 34 run
 # pairs of columns (strips 15 wide: four per row, the last one ragged).
-@pytest.mark.parametrize("mixed", [0, 1])
+@pytest.mark.parametrize("mixed", [0, 1, 2])
 @pytest.mark.parametrize("nrhs", [5, 34])
 def test_pcg_ragged_strips_match_oracle(mixed, nrhs):
     import paper_1307_2895_amd as H

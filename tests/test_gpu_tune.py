@@ -41,7 +41,7 @@ def test_every_variant_matches_oracle(force, case, monkeypatch):
     assert np.max(np.abs(u - ur)) <= 1e-8 * np.max(np.abs(ur))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_autotune_caches_choices_in_tree(prec):
     import paper_1307_2895_amd as H
     dim, n, m = 2, 128, 8
