@@ -1617,6 +1617,11 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       int* live_d = F.mem.get<int>(1);
       const unsigned ng = unsigned(G.ngroup);
       const unsigned chunks = unsigned((ncmax + kCpqrChunk - 1) / kCpqrChunk);
+      // LDS of the update: the reflector's rows when they fit the register path
+      const size_t upd_lds = size_t(std::min(nnmax, 64 * kCpqrRegRows)) * sizeof(T);
+      if (upd_lds > 64 * 1024)
+        HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr_w_update<T>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(upd_lds)));
       hipLaunchKernelGGL(k_cpqr_w_init<T>, dim3(ng, chunks), dim3(kThreads), 0, st,
                          static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, permw, stw);
       for (int j = 0; j < maxsteps; ++j) {
@@ -1624,7 +1629,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                            static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, permw, stw, j,
                            F.eps, tau);
         const unsigned uch = unsigned(std::max(1, (ncmax - j - 1 + kCpqrChunk - 1) / kCpqrChunk));
-        hipLaunchKernelGGL(k_cpqr_w_update<T>, dim3(ng, uch), dim3(kThreads), 0, st,
+        hipLaunchKernelGGL(k_cpqr_w_update<T>, dim3(ng, uch), dim3(kThreads), upd_lds, st,
                            static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, stw, j);
         if ((j & 31) == 31) {   // stop once every group has its rank
           int live = 0;
@@ -1857,7 +1862,8 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
                                 std::chrono::steady_clock::now() - t_start).count();
   }
   // the top block is bracketed by timing events (read after the final
-  // synchronization below)
+  // synchronization below), after the last level's skeleton fronts are queued
+  F.join_skel();
   hipEvent_t top_ev[2] = {nullptr, nullptr};
   if (!F.plan_only)
     for (hipEvent_t& e : top_ev) HIP_CHECK(hipEventCreate(&e));
