@@ -72,6 +72,8 @@ def parse():
                     help="right-hand sides (the workload's first columns) of the CPU sample")
     ap.add_argument("--no-extra", action="store_true",
                     help=f"skip the extra workloads {', '.join(EXTRA_WORKLOADS)}")
+    ap.add_argument("--rank-study", action="store_true",
+                    help="run the rank-predictor study (48 problems, 33 train / 15 test) and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"first run one plain device copy of {CALIB_COPY_BYTES >> 20} MiB "
                          "(scale reference for HBM counters)")
@@ -338,6 +340,135 @@ def sweep_roofline(prof, kernel, traffic):
     }
 
 
+def rank_study(H, torch, train_steps=3000, lr=3e-3):
+    """The learned rank predictor on its own workload: 48 2D problems (16 each
+    at n = 256, 512, 1024, a = 10^(2 U(-1,1)) per link, leaf 16, eps 1e-6).
+    Labels are the skeleton ranks of the FP64 factorization (its skeleton
+    sets equal the oracle's on every decisive front); the network is trained
+    on the GPU with the library's own kernels on problems 0-10 of each size
+    and evaluated on problems 11-15.  Reported: rank MAE against a constant
+    and a worst-case (k = 0) predictor, the fraction of groups whose
+    redundant-unknown count needs more 32-pivot panels than predicted
+    (mis-bucketed), levels re-launched (rebuckets), skeleton-front panel
+    sweeps, host synchronizations and t_factor under each launch policy,
+    and whether every policy reproduces the skeleton sets and F^-1 f."""
+    eps, leaf = 1e-6, 16
+    probs = W.rank_model_problems()
+    trees, data = {}, []
+    t0 = time.perf_counter()
+    for pid, n, seed, split in probs:
+        if n not in trees:
+            trees[n] = H.hifde_build_tree(2, n, leaf, 0)
+        a = [torch.from_numpy(np.ascontiguousarray(x)).cuda()
+             for x in W.make_field(2, n, "loguniform", seed)]
+        F = H.hifde_factor(trees[n], a, None, eps, H.HIFDE_FP64)
+        L = H.hifde_stats(F)["levels"]
+        for level in range(L):
+            f, t = H.hifde_rank_features(F, level)
+            nc = np.array([len(ls[0]) for _, ls in H.hifde_export_sets(F, 2 * level + 1)])
+            data.append((pid, n, split, level, f, t, nc))
+        F.free()
+    t_label = time.perf_counter() - t0
+    Xtr = torch.cat([d[4] for d in data if d[2] == "train"])
+    ttr = torch.cat([d[5] for d in data if d[2] == "train"])
+    # initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)), zero biases,
+    # in the parameter layout of include/hifde.h
+    rng = np.random.default_rng(0)
+    parts = []
+    for fan_out, fan_in in ((64, 16), (64, 64), (1, 64)):
+        lim = 1.0 / np.sqrt(fan_in)
+        parts += [rng.uniform(-lim, lim, fan_out * fan_in), np.zeros(fan_out)]
+    theta = torch.from_numpy(np.concatenate(parts).astype(np.float32)).cuda()
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(1, train_steps + 1):
+        g, loss = H.hifde_mlp_grad(theta, Xtr, ttr)
+        H.hifde_mlp_adam(theta, g, m, v, step, lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    final_loss = float(loss.item())
+    const = float(ttr.mean().item())
+    # held-out accuracy per group
+    err_m, err_c, err_w, mis, ngr = [], [], [], 0, 0
+    for pid, n, split, level, f, t, nc in data:
+        if split != "test" or f.shape[0] == 0:
+            continue
+        y = H.hifde_mlp_forward(theta, f).cpu().numpy().astype(np.float64)
+        k = np.rint(np.exp2(t.cpu().numpy().astype(np.float64)) - 1.0)
+        kh = np.clip(np.floor(np.exp2(y) - 1.0 + 0.5), 0, nc)
+        kc = np.clip(np.floor(np.exp2(const) - 1.0 + 0.5), 0, nc)
+        err_m.append(np.abs(kh - k))
+        err_c.append(np.abs(kc - k))
+        err_w.append(np.abs(k))
+        mis += int(np.sum(np.ceil((nc - k) / 32.0) > np.ceil((nc - kh) / 32.0)))
+        ngr += len(k)
+    err_m, err_c, err_w = (np.concatenate(e) for e in (err_m, err_c, err_w))
+    # launch policies on the held-out problems
+    adversarial = np.zeros(H.HIFDE_RANK_PARAMS, dtype=np.float32)
+    adversarial[-1] = 20.0
+    theta_h = theta.cpu().numpy()
+    pol = {name: {"t_factor_ms": [], "rebuckets": 0, "skel_panels": 0, "host_syncs": 0,
+                  "rank_mae": []} for name in ("sync", "model", "worst", "adversarial")}
+    identical = True
+    for pid, n, seed, split in probs:
+        if split != "test":
+            continue
+        T = trees[n]
+        a = [torch.from_numpy(np.ascontiguousarray(x)).cuda()
+             for x in W.make_field(2, n, "loguniform", seed)]
+        f = torch.from_numpy(W.make_rhs(n * n, 2, 7)).cuda()
+        ref = None
+        for name, flags, model in (("sync", 0, None),
+                                   ("model", H.HIFDE_USE_RANK_MODEL, theta_h),
+                                   ("worst", H.HIFDE_PRESIZE_WORST_CASE, None),
+                                   ("adversarial", H.HIFDE_USE_RANK_MODEL, adversarial)):
+            H.hifde_set_rank_model(T, model)
+            times = []
+            for rep in range(4):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                F = H.hifde_factor(T, a, None, eps, H.HIFDE_FP64, flags=flags)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t1)
+                if rep < 3:
+                    F.free()
+            st = H.hifde_stats(F)
+            L = st["levels"]
+            sets = [[(gid, [x.tolist() for x in ls]) for gid, ls in H.hifde_export_sets(F, l2)]
+                    for l2 in range(1, 2 * L, 2)]
+            u = H.hifde_solve(F, f)
+            if ref is None:
+                ref = (sets, u)
+            elif sets != ref[0] or not torch.equal(u, ref[1]):
+                identical = False
+            F.free()
+            P = pol[name]
+            P["t_factor_ms"].append(1e3 * float(np.median(times[1:])))
+            P["rebuckets"] += st["rebuckets"]
+            P["skel_panels"] += st["skel_panels"]
+            P["host_syncs"] += L          # one rank read-back per level, every policy
+            if name != "sync":
+                P["rank_mae"].append(st["rank_mae"])
+        H.hifde_set_rank_model(T, None)
+    ntest = sum(1 for p in probs if p[3] == "test")
+    out = {
+        "problems": len(probs), "train": len(probs) - ntest, "test": ntest,
+        "labelled_groups": int(sum(len(d[5]) for d in data)),
+        "train_groups": int(Xtr.shape[0]), "test_groups": ngr,
+        "labelling_s": t_label, "train_steps": train_steps, "train_s": t_train,
+        "train_loss": final_loss,
+        "rank_mae": {"model": float(err_m.mean()), "constant": float(err_c.mean()),
+                     "worst_case_k0": float(err_w.mean())},
+        "misbucket_rate": mis / max(1, ngr),
+        "policies": {k: {"t_factor_ms_mean": float(np.mean(v["t_factor_ms"])),
+                         "rebuckets": v["rebuckets"], "skel_panels": v["skel_panels"],
+                         "host_syncs": v["host_syncs"]} for k, v in pol.items()},
+        "identical_sets_and_solutions": identical,
+    }
+    return out
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -351,6 +482,9 @@ def main():
     import torch
     import paper_1307_2895_amd as H
 
+    if args.rank_study:
+        print(json.dumps(rank_study(H, torch)), flush=True)
+        return
     w = W.workload(args.workload)
     N, nrhs = w.N, w.nrhs
     prec = H.PRECISIONS[w.precision]
