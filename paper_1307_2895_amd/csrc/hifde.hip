@@ -1386,12 +1386,20 @@ static void launch_group_front(GroupLevel& G, int nblocks, int ncmax, const int3
                        static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
                        G.perm, G.perm_stride, gsel, kdev, -1);
   } else {
-    const unsigned ch = unsigned((ncmax + kAsmCols - 1) / kAsmCols);
-    for (int phase = 0; phase < 2; ++phase)
-      hipLaunchKernelGGL(k_group_front<T>, dim3(nblocks, ch), dim3(kThreads), 0, st,
-                         static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
-                         static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
-                         G.perm, G.perm_stride, gsel, kdev, phase);
+    // large groups on the matrix cores: output tiles of 64 x 64 (bounds from
+    // |c|, since the ranks may still be on the device)
+    const int64_t tb = (ncmax + kTB - 1) / kTB;
+    const unsigned t0 = unsigned(std::max<int64_t>(1, tb * tb));
+    const unsigned t1 = unsigned(std::max<int64_t>(1, tb * (tb + 1) / 2));
+    if (t0 > 65535) throw Error(HIFDE_EINVAL, "group too large for the skeleton-front grid");
+    hipLaunchKernelGGL(k_group_front_mfma<T>, dim3(nblocks, t0), dim3(kThreads), 0, st,
+                       static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
+                       static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
+                       G.perm, G.perm_stride, gsel, kdev, 0);
+    hipLaunchKernelGGL(k_group_front_mfma<T>, dim3(nblocks, t1), dim3(kThreads), 0, st,
+                       static_cast<T*>(G.fg), static_cast<const T*>(G.gw),
+                       static_cast<const T*>(G.base), static_cast<const T*>(G.tpool), G.groups,
+                       G.perm, G.perm_stride, gsel, kdev, 1);
   }
   HIP_CHECK(hipGetLastError());
 }
