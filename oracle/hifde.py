@@ -61,13 +61,41 @@ def ldl_spd(A: np.ndarray):
     return C / d[None, :], d * d
 
 
-def sparse_elimination(App: np.ndarray, Aqp: np.ndarray):
+class Breakdown(RuntimeError):
+    pass
+
+
+def ldl_sym(A: np.ndarray, tiny: float = 1e-13):
+    """Unpivoted ``A = L D L^T`` of a symmetric block that need not be
+    definite (the indefinite problems of Section 6, Helmholtz-type
+    ``b < 0`` at low frequency): column by column, ``D_j = A_jj - sum_k
+    L_jk^2 D_k`` and ``L_ij = (A_ij - sum_k L_ik L_jk D_k) / D_j``.  A pivot
+    with ``|D_j| <= tiny * max_i |A_ii|`` is a breakdown (no pivoting)."""
+    n = A.shape[0]
+    if n == 0:
+        return np.zeros((0, 0)), np.zeros(0)
+    L = np.eye(n)
+    D = np.zeros(n)
+    scale = float(np.max(np.abs(np.diag(A))))
+    for j in range(n):
+        D[j] = A[j, j] - np.sum(L[j, :j] ** 2 * D[:j])
+        if not abs(D[j]) > tiny * scale:
+            raise Breakdown(f"pivot {j} of an unpivoted LDL^T is {D[j]:.3e}")
+        L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ (L[j, :j] * D[:j])) / D[j]
+    return L, D
+
+
+def _ldl(A: np.ndarray, definite: bool):
+    return ldl_spd(A) if definite else ldl_sym(A)
+
+
+def sparse_elimination(App: np.ndarray, Aqp: np.ndarray, definite: bool = True):
     """Lemma 2.1: ``A_pp = L D L^T``; ``W = D^-1 L^-1 A_qp^T`` is the
     off-diagonal block of the elimination operator ``S_p``; the Schur
     complement update on the front is ``-A_qp A_pp^-1 A_qp^T``.
 
     Returns ``(L, D, W, update)``."""
-    L, D = ldl_spd(App)
+    L, D = _ldl(App, definite)
     if Aqp.shape[0] == 0:
         return L, D, np.zeros((App.shape[0], 0)), np.zeros((0, 0))
     Y = sla.solve_triangular(L, Aqp.T, lower=True, unit_diagonal=True)   # L^-1 A_pq
@@ -129,7 +157,7 @@ def interp_decomp(M: np.ndarray, eps: float, tau: float = 1e-10) -> IDResult:
     return IDResult(k, perm, T, np.array(rdiag))
 
 
-def skeletonize_block(Arr, Asr, Ass, T):
+def skeletonize_block(Arr, Asr, Ass, T, definite: bool = True):
     """Lemma 2.4 on a group ``c = (r, s)`` with ``A_{:,r} ~= A_{:,s} T``:
     ``B_rr = A_rr - T^T A_sr - A_sr^T T + T^T A_ss T``, ``B_sr = A_sr - A_ss T``,
     ``B_rr = L_r D_r L_r^T``, ``W_r = D_r^-1 L_r^-1 B_sr^T`` and the new skeleton
@@ -139,7 +167,7 @@ def skeletonize_block(Arr, Asr, Ass, T):
     Brr = Arr - T.T @ Asr - Asr.T @ T + T.T @ Ass @ T
     Brr = 0.5 * (Brr + Brr.T)
     Bsr = Asr - Ass @ T
-    Lr, Dr = ldl_spd(Brr)
+    Lr, Dr = _ldl(Brr, definite)
     Y = sla.solve_triangular(Lr, Bsr.T, lower=True, unit_diagonal=True)
     Wr = Y / Dr[:, None]
     Bss = Ass - Y.T @ Wr
@@ -243,8 +271,12 @@ def _add_blocks(A: sp.csr_matrix, blocks) -> sp.csr_matrix:
 # ---------------------------------------------------------------------------
 
 def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
-           skip_levels: int = 0, tau: float = 1e-10) -> Factor:
-    """HIF-DE factorization ``A ~= V_0^-T ... V_{L-1/2}^-T D V_{L-1/2}^-1 ... V_0^-1``."""
+           skip_levels: int = 0, tau: float = 1e-10, definite: bool = True) -> Factor:
+    """HIF-DE factorization ``A ~= V_0^-T ... V_{L-1/2}^-T D V_{L-1/2}^-1 ... V_0^-1``.
+
+    ``definite=False`` factors every diagonal block by the unpivoted
+    ``ldl_sym`` (negative pivots allowed): F is then a congruence of the
+    block-diagonal D, symmetric but indefinite, for GMRES (Section 6)."""
     if eps < 0 or eps >= 1:
         raise ValueError("eps must lie in [0, 1)")
     L = tree.num_levels(n, m)
@@ -263,7 +295,7 @@ def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
             q = _neighbors(P, p)
             App = _sub(A, p, p)
             Aqp = _sub(A, q, p)
-            Lc, Dc, Wc, U = sparse_elimination(App, Aqp)
+            Lc, Dc, Wc, U = sparse_elimination(App, Aqp, definite)
             lev.cells.append(CellFactor(cid, p, q, Lc, Dc, Wc))
             if q.size:
                 upd.append((q, U))
@@ -298,7 +330,7 @@ def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
             Arr = Acc[np.ix_(rd_pos, rd_pos)]
             Asr = Acc[np.ix_(sk_pos, rd_pos)]
             Ass = Acc[np.ix_(sk_pos, sk_pos)]
-            Lr, Dr, Wr, Bss = skeletonize_block(Arr, Asr, Ass, T)
+            Lr, Dr, Wr, Bss = skeletonize_block(Arr, Asr, Ass, T, definite)
             sk, rd = c[sk_pos], c[rd_pos]
             lev.groups.append(GroupFactor(gid, c, cN, sk, rd, T, Lr, Dr, Wr, True, idr.rdiag))
             deltas.append((sk, Bss - Ass))
@@ -311,7 +343,7 @@ def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
         levels.append(lev)
     # -- level L: the remaining block D on s_L
     sL = np.nonzero(active)[0]
-    Ltop, Dtop = ldl_spd(_sub(A, sL, sL))
+    Ltop, Dtop = _ldl(_sub(A, sL, sL), definite)
     top = CellFactor(-1, sL, sL[:0].copy(), Ltop, Dtop, np.zeros((sL.size, 0)))
     return Factor(dim, n, m, L, eps, N, levels, top, A0)
 
