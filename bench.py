@@ -72,6 +72,12 @@ def parse():
                     help="right-hand sides (the workload's first columns) of the CPU sample")
     ap.add_argument("--no-extra", action="store_true",
                     help=f"skip the extra workloads {', '.join(EXTRA_WORKLOADS)}")
+    ap.add_argument("--factor-only", action="store_true",
+                    help="only factor the workload (warmup + steps), printing each "
+                         "factorization's time: the command profiles of the factorization use")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="with --factor-only: no autotuning, the default launch variants (a "
+                         "profiler's serialization would skew the tuner's timings)")
     ap.add_argument("--rank-study", action="store_true",
                     help="run the rank-predictor study (48 problems, 33 train / 15 test) and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -486,6 +492,23 @@ def main():
         print(json.dumps(rank_study(H, torch)), flush=True)
         return
     w = W.workload(args.workload)
+    if args.factor_only:
+        a_d = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in W.make_coefficients(w)]
+        tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
+        prec = H.PRECISIONS[w.precision]
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = H.hifde_factor(tree, a_d, None, w.eps, prec,
+                               flags=H.HIFDE_AUTOTUNE if i == 0 and not args.no_tune else 0)
+            torch.cuda.synchronize()
+            st = H.hifde_stats(F)
+            print(json.dumps({"workload": w.name, "run": i, "warmup": i < args.warmup,
+                              "factor_ms": 1e3 * (time.perf_counter() - t0),
+                              "level_ms": st["level_ms"], "top_ms": st["top_ms"],
+                              "factor_gflop": st["factor_flops"] / 1e9}), flush=True)
+            F.free()
+        return
     N, nrhs = w.N, w.nrhs
     prec = H.PRECISIONS[w.precision]
     mixed = prec != H.HIFDE_FP64
