@@ -41,7 +41,7 @@ DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_sol
 CALIB_COPY_BYTES = 512 << 20
 # workloads timed beside the headline one (3D configurations; the last with
 # 256 and with 1 right-hand side on the same factorization)
-EXTRA_WORKLOADS = ("laplace3d_n64", "grf3d_n128")
+EXTRA_WORKLOADS = ("laplace3d_n64", "grf3d_n128", "helmholtz2d_n1024")
 
 
 def dominant_kernel(mixed, nrhs):
@@ -204,12 +204,22 @@ def _subgrid(w, a, f, ns):
 
 
 def _oracle_run(w, a, f, ns):
+    """Oracle factor + solve on the sub-grid: PCG, or for a Helmholtz
+    workload (same b = -k^2) the indefinite factorization and GMRES."""
+    from oracle import gmres as OG
     from oracle import hifde as OH
     from oracle import pcg as OP
     t0 = time.perf_counter()
-    F = OH.factor(w.dim, ns, w.leaf, a, eps=w.eps)
+    if w.wavelengths > 0:
+        F = OH.factor(w.dim, ns, w.leaf, a, b=W.helmholtz_b(ns ** w.dim, w.wavelengths),
+                      eps=w.eps, definite=False)
+    else:
+        F = OH.factor(w.dim, ns, w.leaf, a, eps=w.eps)
     t1 = time.perf_counter()
-    _, its, _ = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 200)
+    if w.wavelengths > 0:
+        _, its, _ = OG.gmres_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 30, 200)
+    else:
+        _, its, _ = OP.pcg_multi(F.A, f, lambda r: OH.solve(F, r), 1e-12, 200)
     t2 = time.perf_counter()
     return t1 - t0, t2 - t1, int(np.max(its))
 
@@ -255,23 +265,34 @@ def cpu_baseline(w, a_full, f_full, n_sample, nrhs):
 
 
 def run_workload(H, torch, w, prec, nrhs_list, steps, warmup, profile_sweep):
-    """Factor + PCG steps of one workload.  The first warmup step autotunes
-    the launch variants of every size bucket (the tree keeps the choices);
-    each timed step factors and then runs PCG for every right-hand-side
-    count in nrhs_list on that factorization.  Returns per-step timings,
-    statistics and the live HIP-event timing of the dominant sweep kernel
-    for the first right-hand-side count."""
+    """Factor + solve steps of one workload (PCG; GMRES for the indefinite
+    Helmholtz workloads).  The first warmup step autotunes the launch
+    variants of every size bucket (the tree keeps the choices); each timed
+    step factors and then solves for every right-hand-side count in
+    nrhs_list on that factorization.  Returns per-step timings, statistics
+    and the live HIP-event timing of the dominant sweep kernel for the first
+    right-hand-side count."""
     N = w.N
     dev = torch.device("cuda:0")
     a_d = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in W.make_coefficients(w)]
+    b_h = W.make_b(w)
+    b_d = None if b_h is None else torch.from_numpy(b_h).to(dev)
+    indefinite = b_h is not None
+    flags = H.HIFDE_INDEFINITE if indefinite else 0
     f_d = {k: torch.from_numpy(W.make_rhs(N, k, w.seed_f)).to(dev) for k in nrhs_list}
     tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
     prof = {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0}
 
+    def solve(F, f):
+        if indefinite:
+            return H.hifde_gmres(F, f, tol=1e-12, restart=30, maxit=200)
+        return H.hifde_pcg(F, f, tol=1e-12, maxit=200)
+
     def step(profile=False, tune=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F = H.hifde_factor(tree, a_d, None, w.eps, prec, flags=H.HIFDE_AUTOTUNE if tune else 0)
+        F = H.hifde_factor(tree, a_d, b_d, w.eps, prec,
+                           flags=flags | (H.HIFDE_AUTOTUNE if tune else 0))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         res = {"factor_s": t1 - t0, "stats": H.hifde_stats(F), "pcg": {}}
@@ -280,7 +301,7 @@ def run_workload(H, torch, w, prec, nrhs_list, steps, warmup, profile_sweep):
                 H.hifde_profile(F, 1 << H.HIFDE_PROF_SWEEP_UP_ONE, -1)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            u, its, rel = H.hifde_pcg(F, f_d[k], tol=1e-12, maxit=200)
+            u, its, rel = solve(F, f_d[k])
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             if profile and i == 0:
@@ -302,7 +323,8 @@ def run_workload(H, torch, w, prec, nrhs_list, steps, warmup, profile_sweep):
     for k in range(steps):
         r = step(profile=profile_sweep)
         out.append(r)
-        pc = ", ".join(f"pcg[{n}] {1e3 * v[0]:.1f} ms ({int(v[1].max())} it)"
+        sname = "gmres" if indefinite else "pcg"
+        pc = ", ".join(f"{sname}[{n}] {1e3 * v[0]:.1f} ms ({int(v[1].max())} it)"
                        for n, v in r["pcg"].items())
         print(f"{w.name} step {k}: factor {1e3 * r['factor_s']:.1f} ms, {pc}",
               file=sys.stderr, flush=True)
@@ -494,13 +516,16 @@ def main():
     w = W.workload(args.workload)
     if args.factor_only:
         a_d = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in W.make_coefficients(w)]
+        b_h = W.make_b(w)
+        b_d = None if b_h is None else torch.from_numpy(b_h).cuda()
+        fl = 0 if b_h is None else H.HIFDE_INDEFINITE
         tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
         prec = H.PRECISIONS[w.precision]
         for i in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            F = H.hifde_factor(tree, a_d, None, w.eps, prec,
-                               flags=H.HIFDE_AUTOTUNE if i == 0 and not args.no_tune else 0)
+            F = H.hifde_factor(tree, a_d, b_d, w.eps, prec,
+                               flags=fl | (H.HIFDE_AUTOTUNE if i == 0 and not args.no_tune else 0))
             torch.cuda.synchronize()
             st = H.hifde_stats(F)
             print(json.dumps({"workload": w.name, "run": i, "warmup": i < args.warmup,
@@ -596,16 +621,19 @@ def main():
             re_, _, pe = run_workload(H, torch, we, pe_, counts, 1, 1, True)
             r = re_[0]
             tfe = r["factor_s"]
+            sv = "gmres" if we.wavelengths > 0 else "pcg"
             item = {"workload": name, "dim": we.dim, "n": we.n, "N": we.N, "leaf": we.leaf,
                     "eps": we.eps, "field": we.field, "precision": we.precision,
-                    "factor_ms": 1e3 * tfe, "factor_dof_per_s": we.N / tfe,
+                    "solver": sv, "factor_ms": 1e3 * tfe, "factor_dof_per_s": we.N / tfe,
                     "top_size": r["stats"]["top_size"],
                     "factor_roofline": factor_roofline(r["stats"], tfe, me), "solves": []}
+            if we.wavelengths > 0:
+                item["wavelengths"] = we.wavelengths
             for k in counts:
                 t, its, rel = r["pcg"][k]
                 item["solves"].append({
-                    "nrhs": k, "pcg_ms": 1e3 * t, "pcg_iters_max": int(np.max(its)),
-                    "pcg_relres_max": float(np.max(rel)),
+                    "nrhs": k, f"{sv}_ms": 1e3 * t, f"{sv}_iters_max": int(np.max(its)),
+                    f"{sv}_relres_max": float(np.max(rel)),
                     "solve_dof_rhs_per_s": we.N * k / t,
                     "step_dof_rhs_per_s": we.N * k / (tfe + t)})
             item["roofline"] = sweep_roofline(pe, dominant_kernel(me, counts[0]), None)

@@ -46,8 +46,9 @@ typedef enum {
   HIFDE_EINVAL = -1,   /* invalid argument                                  */
   HIFDE_ENOMEM = -2,   /* device or host allocation failed                  */
   HIFDE_EDEVICE = -3,  /* a HIP runtime call failed                         */
-  HIFDE_ENOTSPD = -4,  /* a diagonal block had a non-positive pivot         */
-  HIFDE_ENOCONV = -5,  /* PCG did not reach the tolerance within maxit      */
+  HIFDE_ENOTSPD = -4,  /* a diagonal block had a non-positive pivot (with
+                          HIFDE_INDEFINITE: a zero or non-finite one)     */
+  HIFDE_ENOCONV = -5,  /* PCG or GMRES missed the tolerance within maxit   */
   HIFDE_ESTATE = -6    /* handle in the wrong state for this call           */
 } hifde_status;
 
@@ -83,10 +84,16 @@ enum {
   HIFDE_PRESIZE_WORST_CASE = 64u, /* as HIFDE_USE_RANK_MODEL with every rank
                                    assumed 0 (the largest possible fronts):
                                    the comparison point of the predictor    */
-  HIFDE_SWEEP_ROW_TILES = 128u  /* F^-1 sweeps in the row-tile form only (no
+  HIFDE_SWEEP_ROW_TILES = 128u, /* F^-1 sweeps in the row-tile form only (no
                                    whole-front launches, interpolation as
                                    separate launches); the results are
                                    bitwise the same                         */
+  HIFDE_INDEFINITE = 256u       /* A may be indefinite (b < 0, Helmholtz-type
+                                   problems, Section 5): the LDL^T of every
+                                   diagonal block accepts negative pivots
+                                   (no pivoting; a zero or non-finite pivot
+                                   fails with HIFDE_ENOTSPD).  Solve with
+                                   hifde_gmres; hifde_pcg refuses the factor */
 };
 
 /* Maximum number of tree levels reported by hifde_stats. */
@@ -164,7 +171,8 @@ int hifde_tree_set_memory_limit(hifde_tree_t tree, int64_t bytes);
  * reference to a or b.
  * EINVAL: eps outside [0, 1), NULL a[k], non-positive or non-finite a
  * (checked on the device), non-finite b.  ENOTSPD: a pivot of a diagonal
- * block was not positive; hifde_last_error() names the level and block.
+ * block was not positive (with HIFDE_INDEFINITE: was zero or not finite);
+ * hifde_last_error() names the level and block.
  * The pivots of each level are read with that level's skeleton ranks, so
  * the factorization stops at the level after the failing block (at the end
  * when no level is skeletonized).  ENOMEM: the device, or the tree's cap
@@ -188,12 +196,37 @@ int hifde_solve(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
  * other overlap).  iters[nrhs], relres[nrhs]: HOST,
  * filled with the iteration count and the true relative residual
  * ||f - A u|| / ||f|| of each column.
- * ENOCONV: some column missed tol; iters, relres and u hold the last iterate. */
+ * ENOCONV: some column missed tol; iters, relres and u hold the last iterate.
+ * ESTATE: F was factored with HIFDE_INDEFINITE (conjugate gradients needs a
+ * definite operator: use hifde_gmres). */
 int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
               double* u, int64_t ldu, double tol, int maxit, int* iters,
               double* relres, void* hip_stream);
 
-/* y = A x with the assembled stencil (the operator PCG uses).  DEVICE,
+/* Solve A u = f by GMRES with F^-1 as right preconditioner (the paper's
+ * solver for indefinite problems, Section 5), from u = 0, in double
+ * precision, one independent iteration per column.  Each step takes
+ * z_k = F^-1 v_k and A z_k, orthogonalizes against the basis by modified
+ * Gram-Schmidt and updates the Hessenberg least-squares problem by Givens
+ * rotations; every `restart` steps (and at the end) u += Z y with the kept
+ * z_k (for the fixed linear F^-1 the same as F^-1 (V y); for the float
+ * factor it keeps A Z = V H exact in double, the flexible form), and the
+ * next cycle starts from the true residual.  It stops when the residual
+ * estimate reaches tol ||f|| (or the true residual does, at a restart) or
+ * after maxit steps in all.  Any factor works (definite or not).
+ * f, u: DEVICE, N x nrhs column-major; f may equal u when ldf == ldu (no
+ * other overlap).  iters[nrhs], relres[nrhs]: HOST, filled with the step
+ * count and the true relative residual ||f - A u|| / ||f|| of each column.
+ * Device memory: (restart + 1) N nrhs doubles for the basis and restart
+ * N nrhs elements of the factor's sweep type (float or double) for the z_k.
+ * EINVAL: nrhs < 1, ld < N, NULL pointers, restart < 1, maxit < 1, tol not
+ * finite and positive.  ENOCONV: some column missed tol; iters, relres and u hold
+ * the last iterate. */
+int hifde_gmres(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf,
+                double* u, int64_t ldu, double tol, int restart, int maxit,
+                int* iters, double* relres, void* hip_stream);
+
+/* y = A x with the assembled stencil (the operator PCG and GMRES use).  DEVICE,
  * N x nrhs column-major. */
 int hifde_matvec(hifde_factor_t F, int64_t nrhs, const double* x, int64_t ldx,
                  double* y, int64_t ldy, void* hip_stream);

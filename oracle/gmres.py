@@ -1,5 +1,5 @@
 """Restarted GMRES with right preconditioning (the Krylov solver the paper
-pairs with the factorization for indefinite problems, Section 6).
+pairs with the factorization for indefinite problems, Section 5).
 
 For A x = f from x0 = 0: with z = M r the Arnoldi process builds an
 orthonormal basis V of the Krylov space of A M (modified Gram-Schmidt), the

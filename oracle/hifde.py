@@ -67,7 +67,7 @@ class Breakdown(RuntimeError):
 
 def ldl_sym(A: np.ndarray, tiny: float = 1e-13):
     """Unpivoted ``A = L D L^T`` of a symmetric block that need not be
-    definite (the indefinite problems of Section 6, Helmholtz-type
+    definite (the indefinite problems of Section 5, Helmholtz-type
     ``b < 0`` at low frequency): column by column, ``D_j = A_jj - sum_k
     L_jk^2 D_k`` and ``L_ij = (A_ij - sum_k L_ik L_jk D_k) / D_j``.  A pivot
     with ``|D_j| <= tiny * max_i |A_ii|`` is a breakdown (no pivoting)."""
@@ -276,7 +276,7 @@ def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
 
     ``definite=False`` factors every diagonal block by the unpivoted
     ``ldl_sym`` (negative pivots allowed): F is then a congruence of the
-    block-diagonal D, symmetric but indefinite, for GMRES (Section 6)."""
+    block-diagonal D, symmetric but indefinite, for GMRES (Section 5)."""
     if eps < 0 or eps >= 1:
         raise ValueError("eps must lie in [0, 1)")
     L = tree.num_levels(n, m)

@@ -2,7 +2,7 @@
 AMD MI355X (gfx950).
 
 The Python functions mirror the C ABI of ``include/hifde.h`` one to one and
-only marshal arguments; the factorization, F^-1 sweeps and PCG run in the
+only marshal arguments; the factorization, F^-1 sweeps, PCG and GMRES run in the
 HIP library ``libhifde.so``.  torch supplies device memory and the stream.
 """
 from __future__ import annotations
@@ -14,7 +14,7 @@ import numpy as np
 from ._lib import (  # noqa: F401
     HIFDE_FP64, HIFDE_MIXED, HIFDE_MIXED_ELIM64, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH, HIFDE_USE_RANK_MODEL,
     HIFDE_AUTOTUNE,
-    HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES,
+    HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES, HIFDE_INDEFINITE,
     HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE, HIFDE_ENOMEM,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
@@ -147,6 +147,25 @@ def hifde_pcg(F: Factor, f, tol: float = 1e-12, maxit: int = 200, stream=None,
     rel = (C.c_double * nrhs)()
     rc = lib().hifde_pcg(F._h, nrhs, _dptr(fc), N, _dptr(u), N, float(tol), int(maxit), its, rel,
                          _stream(stream))
+    if rc != 0 and (raise_on_noconv or rc != HIFDE_ENOCONV):
+        check(rc)
+    out = u.reshape(shape) if len(shape) == 1 else u.t()
+    return out, np.array(its[:]), np.array(rel[:])
+
+
+def hifde_gmres(F: Factor, f, tol: float = 1e-12, restart: int = 30, maxit: int = 200,
+                stream=None, raise_on_noconv: bool = True):
+    """Restarted GMRES with right preconditioner F^-1.  Returns
+    ``(u, iters, relres)``."""
+    import torch
+    N = F.N
+    fc, shape = _as_colmajor(f, N)
+    nrhs = fc.shape[0]
+    u = torch.empty_like(fc)
+    its = (C.c_int * nrhs)()
+    rel = (C.c_double * nrhs)()
+    rc = lib().hifde_gmres(F._h, nrhs, _dptr(fc), N, _dptr(u), N, float(tol), int(restart),
+                           int(maxit), its, rel, _stream(stream))
     if rc != 0 and (raise_on_noconv or rc != HIFDE_ENOCONV):
         check(rc)
     out = u.reshape(shape) if len(shape) == 1 else u.t()

@@ -21,13 +21,14 @@ HIFDE_FP64, HIFDE_MIXED, HIFDE_MIXED_ELIM64 = 0, 1, 2
 HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_AUTOTUNE, HIFDE_NO_GRAPH = 1, 4, 8, 16
 HIFDE_PRESIZE_WORST_CASE = 64
 HIFDE_SWEEP_ROW_TILES = 128
+HIFDE_INDEFINITE = 256
 HIFDE_MAX_LEVELS = 24
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD",
                 -5: "ENOCONV", -6: "ESTATE"}
 
 EXPORTED = [
-    "hifde_build_tree", "hifde_factor", "hifde_solve", "hifde_pcg", "hifde_matvec",
+    "hifde_build_tree", "hifde_factor", "hifde_solve", "hifde_pcg", "hifde_gmres", "hifde_matvec",
     "hifde_stats", "hifde_export_sets", "hifde_plan_replay", "hifde_profile",
     "hifde_profile_read", "hifde_mlp_workspace", "hifde_mlp_forward", "hifde_mlp_grad",
     "hifde_mlp_grad_noalloc", "hifde_mlp_adam", "hifde_rank_features", "hifde_set_rank_model",
@@ -113,6 +114,8 @@ def lib():
     L.hifde_matvec.argtypes = [vp, i64, vp, i64, vp, i64, vp]
     L.hifde_pcg.argtypes = [vp, i64, vp, i64, vp, i64, dbl, i32, C.POINTER(C.c_int),
                             C.POINTER(C.c_double), vp]
+    L.hifde_gmres.argtypes = [vp, i64, vp, i64, vp, i64, dbl, i32, i32, C.POINTER(C.c_int),
+                              C.POINTER(C.c_double), vp]
     L.hifde_stats.argtypes = [vp, C.POINTER(Stats)]
     L.hifde_export_sets.argtypes = [vp, i32, C.POINTER(Sets)]
     L.hifde_plan_replay.argtypes = [vp, vp, C.POINTER(vp)]

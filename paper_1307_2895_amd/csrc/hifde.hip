@@ -516,6 +516,7 @@ struct hifde_factor_s {
   Geom g;
   hifde_precision prec = HIFDE_FP64;
   double eps = 0.0;
+  bool definite = true;        // without HIFDE_INDEFINITE: pivots must be positive
   bool plan_only = false;
   std::unique_ptr<Planner> planner;
   std::vector<CellLevel> cl;   // L + 1 entries (last = top)
@@ -527,6 +528,7 @@ struct hifde_factor_s {
   DevMem X, Z, C;
   DevMem pcg;
   int64_t pcg_rhs = 0;
+  DevMem gm;                   // GMRES basis, kept z_k and scalars
   // kernel timing (hifde_profile)
   struct ProfEvent {
     hipEvent_t a = nullptr, b = nullptr;
@@ -869,8 +871,8 @@ enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_VARIANTS = 2 };
 // of panel j cover only the fronts that still have pivots there.
 template <typename T>
 static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
-                        int* info_d, hipStream_t st, bool bounds = false, bool sorted = false,
-                        int variant = LDL_MFMA) {
+                        int* info_d, int definite, hipStream_t st, bool bounds = false,
+                        bool sorted = false, int variant = LDL_MFMA) {
   if (fh.empty()) return;
   int pmax = 0;
   for (const auto& f : fh) pmax = std::max(pmax, f.p);
@@ -899,7 +901,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     // one wavefront per diagonal block: the 32 dependent steps are latency
     // bound, so many small work-groups per CU do better than few large ones
     hipLaunchKernelGGL(k_ldl_diag<T>, dim3(nf), dim3(kDiagThreads), 0, st, pool, fronts_d, j0,
-                       info_d);
+                       info_d, definite);
     if (maxr > 0)
       hipLaunchKernelGGL(k_ldl_rows<T>, dim3(front_tile_grid(nf, maxr, "panel grid")),
                          dim3(kThreads), 0, st, pool, fronts_d, j0, int(nf), int(maxr));
@@ -1254,9 +1256,9 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   const int var = tune_choice(
       F, tune_key(FAM_LDL, int(sizeof(T)), S.pmax, S.smax, S.ncell), LDL_VARIANTS, LDL_MFMA, D.pool,
       size_t(S.elems) * sizeof(T), st, [&](int v) {
-        batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, v);
+        batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, v);
       });
-  batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, st, false, true, var);
+  batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, var);
   // The apply form and its packed copy are read by the sweeps only: they run
   // on the side stream after this level's IDs, beside the host's skeleton
   // bookkeeping and the next level's planning.  They touch the first p
@@ -1285,22 +1287,23 @@ static void check_input(hifde_factor_s& F, hipStream_t st) {
   if (h & 2) throw Error(HIFDE_EINVAL, "b must be finite");
 }
 
-static void report_info(const std::vector<int>& h, const char* what, int l) {
+static void report_info(const std::vector<int>& h, const char* what, int l, bool definite) {
   for (size_t i = 0; i < h.size(); ++i)
     if (h[i] != 0) {
       char buf[200];
-      snprintf(buf, sizeof buf, "non-positive pivot in %s %zu of level %d (panel at %d)", what, i, l,
-               h[i] - 1);
+      snprintf(buf, sizeof buf, "%s pivot in %s %zu of level %d (panel at %d)",
+               definite ? "non-positive" : "zero or non-finite", what, i, l, h[i] - 1);
       throw Error(HIFDE_ENOTSPD, buf);
     }
 }
 
-static void check_info(const int* info, size_t n, const char* what, int l, hipStream_t st) {
+static void check_info(const int* info, size_t n, const char* what, int l, bool definite,
+                       hipStream_t st) {
   if (n == 0) return;
   std::vector<int> h(n);
   HIP_CHECK(hipMemcpyAsync(h.data(), info, n * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
-  report_info(h, what, l);
+  report_info(h, what, l, definite);
 }
 
 // Pivot flags of the level-l cells and of the level l-1/2 skeleton fronts,
@@ -1325,9 +1328,9 @@ struct LevelPivots {
                                  hipMemcpyDeviceToHost, st));
     }
   }
-  void check(int l) const {   // after the stream has synchronized
-    report_info(cells, "cell", l);
-    report_info(groups, "group", l - 1);
+  void check(int l, bool definite) const {   // after the stream has synchronized
+    report_info(cells, "cell", l, definite);
+    report_info(groups, "group", l - 1, definite);
   }
 };
 
@@ -1485,9 +1488,9 @@ static void skeleton_fronts(hifde_factor_s& F, GroupLevel& G, const Level& lev,
     const int var = tune_choice(
         F, tune_key(FAM_LDL, int(sizeof(T)), pmx, smx, G.nskel), LDL_VARIANTS, LDL_MFMA, G.fg,
         size_t(fg_off) * sizeof(T), st, [&](int v) {
-          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, v);
+          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, v);
         });
-    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, st, false, true, var);
+    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, var);
     const int ivar = tune_choice(
         F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 2, 1, G.fg,
         size_t(fg_off) * sizeof(T), st,
@@ -1714,7 +1717,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     HIP_CHECK(hipMemsetAsync(G.fg, 0, size_t(fg_all) * sizeof(T), st));
     HIP_CHECK(hipMemsetAsync(G.info, 0, sizeof(int) * G.ngroup, st));
     launch_group_front<T>(G, G.ngroup, ncmax, static_cast<const int32_t*>(nullptr), G.kout, st);
-    batched_ldl<T>(static_cast<T*>(G.fg), fall, G.fgfronts, G.info, st, true);
+    batched_ldl<T>(static_cast<T*>(G.fg), fall, G.fgfronts, G.info, F.definite, st, true);
     apply_form<T>(F.mem, static_cast<T*>(G.fg), fall, G.fgfronts, st, true);
     F.skel_panels += (bound + kNB - 1) / kNB;
     pack_fronts<T>(F.mem, static_cast<const T*>(G.fg), fall, G.fgfronts, sall, &G.pk, &G.pt,
@@ -1752,7 +1755,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   HIP_CHECK(hipStreamSynchronize(st));
   tm.mark("  wait for IDs", l);
   check_input(F, st);
-  piv.check(l);
+  piv.check(l, F.definite);
   // record skeletons; build the skeleton fronts
   int64_t fg_off = 0;
   G.gsel_h.clear();
@@ -1908,10 +1911,11 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   check_input(F, st);
   // pivot checks of every level at once (one synchronization)
   for (int l = 0; l <= L; ++l) {
-    check_info(F.cl[l].info, F.cl[l].st->fh.size(), l == L ? "top block" : "cell", l, st);
+    check_info(F.cl[l].info, F.cl[l].st->fh.size(), l == L ? "top block" : "cell", l,
+               F.definite, st);
     if (l < L && F.gl[l].info) {
       const size_t ni = F.presize ? size_t(F.gl[l].ngroup) : size_t(F.gl[l].nskel);
-      if (ni > 0) check_info(F.gl[l].info, ni, "group", l, st);
+      if (ni > 0) check_info(F.gl[l].info, ni, "group", l, F.definite, st);
     }
   }
   tm.mark("pivot checks", L);
@@ -2534,6 +2538,170 @@ static bool run_pcg(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ld
               : run_pcg_w<TR, 1, 3>(F, nrhs, f, ldf, u, ldu, tol, maxit, iters, relres, st);
 }
 
+// GMRES with F^-1 as right preconditioner (Section 5), restarted every m
+// steps, one independent iteration per column, vectors unknown-major in
+// double; TR is the type of the preconditioner's vectors.  The basis and
+// the inner products stay on the device; the host reads each step's
+// Hessenberg column (m + 2 values per column at most) and applies the
+// Givens rotations.  All live columns step together: a column that has
+// converged gets zero basis vectors (its h is 0), so its later steps add
+// nothing.  Returns whether every column reached tol.
+template <typename TR>
+static bool run_gmres(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t ldf, double* u,
+                      int64_t ldu, double tol, int m, int maxit, int* iters, double* relres,
+                      hipStream_t st) {
+  using TP = typename std::conditional<sizeof(TR) == 4, float, double>::type;
+  const int64_t N = F.g.N, n = N * nrhs;
+  const int nr = int(nrhs);
+  const size_t need = (size_t(m) + 3) * size_t(n) * 8 + size_t(m) * size_t(n) * sizeof(TR) +
+                      (size_t(kGmBlocks) * 2 + size_t(m) * 2 + 3) * size_t(nr) * 8;
+  if (F.gm.bytes < need) F.gm.alloc(need);
+  ensure_X(F, nrhs);
+  TR* X = F.X.as<TR>();
+  TR* Zs = F.Z.as<TR>();
+  double* V = F.gm.as<double>();                 // v_0 .. v_m
+  double* w = V + size_t(m + 1) * n;
+  double* x = w + n;
+  double* part = x + n;                          // kGmBlocks x 2 x nr
+  double* h = part + size_t(kGmBlocks) * 2 * nr; // (m + 2) x nr
+  double* den = h + size_t(m + 2) * nr;          // nr
+  double* Yd = den + nr;                         // m x nr
+  TR* Zk = reinterpret_cast<TR*>(Yd + size_t(m) * nr);   // z_0 .. z_{m-1}
+  const unsigned nb = unsigned(std::min<int64_t>(kGmBlocks, std::max<int64_t>(1, nblk(n))));
+  const unsigned ne = nblk(n);
+  const int dim = F.g.dim;
+  const int64_t side = F.g.n;
+  const double* diag = F.diag.as<double>();
+  const double* offd = F.offd.as<double>();
+  auto mgs = [&](const double* coef, const double* vprev, const double* v, double* out) {
+    hipLaunchKernelGGL(k_gm_mgs, dim3(nb), dim3(kThreads), 0, st, N, nr, coef, vprev, v, w, part);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, part, out);
+  };
+  auto read_h = [&](std::vector<double>& hh, int rows) {
+    HIP_CHECK(hipMemcpyAsync(hh.data(), h, size_t(rows) * nr * 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  };
+  const size_t ldh = size_t(m) + 1;              // H of column c: Hs[c][i + j ldh]
+  std::vector<double> hh(size_t(m + 2) * nr), nf(nr, 0.0), denh(nr), Yh(size_t(m) * nr);
+  std::vector<double> Hs(ldh * m * nr), cs(size_t(m) * nr), sn(size_t(m) * nr), g(ldh * nr);
+  std::vector<int> live(nr, 1), act(nr, 0), kd(nr, 0), its(nr, 0);
+  HIP_CHECK(hipMemsetAsync(x, 0, size_t(n) * 8, st));
+  int it = 0;
+  for (bool first = true;; first = false) {
+    // r = f - A x (the true residual) into w, and its norm
+    hipLaunchKernelGGL(k_gm_residual, dim3(ne), dim3(kThreads), 0, st, N, nr, dim, side, diag,
+                       offd, f, ldf, x, w);
+    mgs(nullptr, nullptr, nullptr, h);
+    read_h(hh, 1);
+    bool any = false;
+    for (int c = 0; c < nr; ++c) {
+      const double beta = std::sqrt(hh[c]);
+      if (first) {
+        nf[c] = beta;
+        if (beta == 0.0) live[c] = 0;
+      }
+      if (live[c] && beta <= tol * nf[c]) live[c] = 0;
+      act[c] = live[c];
+      kd[c] = 0;
+      denh[c] = act[c] ? beta : 0.0;
+      g[c * ldh] = beta;
+      any = any || act[c];
+    }
+    if (!any || it >= maxit) break;   // hh holds ||f - A x||^2 of the final x
+    HIP_CHECK(hipMemcpyAsync(den, denh.data(), size_t(nr) * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gm_div, dim3(ne), dim3(kThreads), 0, st, n, nr, den, w, V);
+    for (int k = 0; k < m; ++k) {
+      ++it;
+      // w = A z_k, z_k = F^-1 v_k (kept for the update of x)
+      hipLaunchKernelGGL((k_gm_convert<TR>), dim3(ne), dim3(kThreads), 0, st, n,
+                         V + size_t(k) * n, X);
+      apply_inverse_g<TP, TR>(F, X, Zs, nr, st);
+      hipLaunchKernelGGL((k_gm_matvec<TR>), dim3(ne), dim3(kThreads), 0, st, N, nr, dim, side,
+                         diag, offd, X, Zk + size_t(k) * n, w);
+      // modified Gram-Schmidt: h_ik = v_i . w, w -= h_ik v_i in turn, then
+      // ||w||^2
+      for (int i = 0; i <= k; ++i)
+        mgs(i ? h + size_t(i - 1) * nr : nullptr, i ? V + size_t(i - 1) * n : nullptr,
+            V + size_t(i) * n, h + size_t(i) * nr);
+      mgs(h + size_t(k) * nr, V + size_t(k) * n, nullptr, h + size_t(k + 1) * nr);
+      read_h(hh, k + 2);
+      bool anyact = false;
+      for (int c = 0; c < nr; ++c) {
+        if (!act[c]) {
+          denh[c] = 0.0;
+          continue;
+        }
+        double* H = &Hs[size_t(c) * ldh * m];
+        double* col = H + size_t(k) * ldh;
+        for (int i = 0; i <= k; ++i) col[i] = hh[size_t(i) * nr + c];
+        col[k + 1] = std::sqrt(hh[size_t(k + 1) * nr + c]);
+        denh[c] = col[k + 1] > 0.0 ? col[k + 1] : 0.0;
+        double* csc = &cs[size_t(c) * m];
+        double* snc = &sn[size_t(c) * m];
+        double* gc = &g[size_t(c) * ldh];
+        for (int i = 0; i < k; ++i) {   // the earlier rotations on the new column
+          const double t = csc[i] * col[i] + snc[i] * col[i + 1];
+          col[i + 1] = -snc[i] * col[i] + csc[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double rho = std::hypot(col[k], col[k + 1]);
+        if (!(rho > 0.0)) {   // breakdown without progress: end the cycle here
+          act[c] = 0;
+          denh[c] = 0.0;
+          continue;
+        }
+        csc[k] = col[k] / rho;
+        snc[k] = col[k + 1] / rho;
+        col[k] = rho;
+        col[k + 1] = 0.0;
+        gc[k + 1] = -snc[k] * gc[k];
+        gc[k] = csc[k] * gc[k];
+        its[c] = it;
+        kd[c] = k + 1;
+        if (std::fabs(gc[k + 1]) <= tol * nf[c] || it >= maxit) {
+          act[c] = 0;
+          denh[c] = 0.0;
+        }
+        anyact = anyact || act[c];
+      }
+      if (!anyact) break;
+      HIP_CHECK(hipMemcpyAsync(den, denh.data(), size_t(nr) * 8, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_gm_div, dim3(ne), dim3(kThreads), 0, st, n, nr, den, w,
+                         V + size_t(k + 1) * n);
+    }
+    // y = R^-1 g (back substitution) per column, x += Z y
+    int kmax = 0;
+    std::fill(Yh.begin(), Yh.end(), 0.0);
+    for (int c = 0; c < nr; ++c) {
+      const int kc = kd[c];
+      kmax = std::max(kmax, kc);
+      const double* H = &Hs[size_t(c) * ldh * m];
+      const double* gc = &g[size_t(c) * ldh];
+      for (int i = kc - 1; i >= 0; --i) {
+        double t = gc[i];
+        for (int j = i + 1; j < kc; ++j) t -= H[i + size_t(j) * ldh] * Yh[size_t(j) * nr + c];
+        Yh[size_t(i) * nr + c] = t / H[i + size_t(i) * ldh];
+      }
+      if (kc > 0 && std::fabs(gc[kc]) <= tol * nf[c]) live[c] = 0;
+    }
+    if (kmax > 0) {
+      HIP_CHECK(hipMemcpyAsync(Yd, Yh.data(), size_t(kmax) * nr * 8, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL((k_gm_combine<TR>), dim3(ne), dim3(kThreads), 0, st, n, nr, kmax, Yd, Zk,
+                         x);
+    }
+  }
+  hipLaunchKernelGGL(k_to_colmajor<double>, dim3(ne), dim3(kThreads), 0, st, N, nr, x, u, ldu);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));
+  bool converged = true;
+  for (int c = 0; c < nr; ++c) {
+    iters[c] = its[c];
+    relres[c] = nf[c] > 0.0 ? std::sqrt(hh[c]) / nf[c] : 0.0;
+    if (live[c]) converged = false;
+  }
+  return converged;
+}
+
 // Stencil assembly and the factorization of every level into F.
 static void build_factor(hifde_factor_s& F, hifde_tree_s* tree, const double* const* a,
                          const double* b, double eps, hifde_precision prec, hipStream_t st) {
@@ -2680,7 +2848,8 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
   if (prec != HIFDE_FP64 && prec != HIFDE_MIXED && prec != HIFDE_MIXED_ELIM64)
     return fail(HIFDE_EINVAL, "unknown precision");
   if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_AUTOTUNE |
-                        HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE | HIFDE_SWEEP_ROW_TILES))
+                        HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE | HIFDE_SWEEP_ROW_TILES |
+                        HIFDE_INDEFINITE))
     return fail(HIFDE_EINVAL, "unknown flags");
   if ((flags & HIFDE_USE_RANK_MODEL) && (flags & HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "HIFDE_USE_RANK_MODEL and HIFDE_PRESIZE_WORST_CASE exclude each other");
@@ -2696,6 +2865,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     F->presize = presize;
     F->model = presize == 1 ? tree->model_d.as<float>() : nullptr;
     F->autotune = (flags & HIFDE_AUTOTUNE) != 0;
+    F->definite = !(flags & HIFDE_INDEFINITE);
     F->tree = tree;
     F->use_pool(tree->pool);
     build_factor(*F, tree, a, b, eps, prec, st);
@@ -2709,6 +2879,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
       F2.use_pool(tree->pool);
       F2.presize = presize;
       F2.model = F->model;
+      F2.definite = F->definite;
       F2.tree = tree;
       build_factor(F2, tree, a, b, eps, prec, st);
       compare_factors(*F, F2, st);
@@ -3028,6 +3199,8 @@ int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, doub
   if (F->plan_only) return fail(HIFDE_ESTATE, "factor holds no numerical data");
   if (nrhs < 1 || ldf < F->g.N || ldu < F->g.N) return fail(HIFDE_EINVAL, "bad nrhs or ld");
   if (!(tol > 0.0) || maxit < 1) return fail(HIFDE_EINVAL, "tol must be > 0 and maxit >= 1");
+  if (!F->definite)
+    return fail(HIFDE_ESTATE, "the factor is indefinite (HIFDE_INDEFINITE): use hifde_gmres");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   bool converged = true;
   int rc = guarded([&] {
@@ -3038,6 +3211,29 @@ int hifde_pcg(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, doub
   });
   if (rc != HIFDE_OK) return rc;
   if (!converged) return fail(HIFDE_ENOCONV, "PCG did not reach the tolerance within maxit");
+  return HIFDE_OK;
+}
+
+int hifde_gmres(hifde_factor_t F, int64_t nrhs, const double* f, int64_t ldf, double* u,
+                int64_t ldu, double tol, int restart, int maxit, int* iters, double* relres,
+                void* hip_stream) {
+  if (!F || !f || !u || !iters || !relres) return fail(HIFDE_EINVAL, "NULL argument");
+  if (F->plan_only) return fail(HIFDE_ESTATE, "factor holds no numerical data");
+  if (nrhs < 1 || ldf < F->g.N || ldu < F->g.N) return fail(HIFDE_EINVAL, "bad nrhs or ld");
+  if (!(tol > 0.0 && tol < HUGE_VAL) || maxit < 1 || restart < 1)
+    return fail(HIFDE_EINVAL, "tol must be finite and > 0, maxit and restart >= 1");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  bool converged = true;
+  int rc = guarded([&] {
+    if (float_sweeps(*F))
+      converged =
+          run_gmres<float>(*F, nrhs, f, ldf, u, ldu, tol, restart, maxit, iters, relres, st);
+    else
+      converged =
+          run_gmres<double>(*F, nrhs, f, ldf, u, ldu, tol, restart, maxit, iters, relres, st);
+  });
+  if (rc != HIFDE_OK) return rc;
+  if (!converged) return fail(HIFDE_ENOCONV, "GMRES did not reach the tolerance within maxit");
   return HIFDE_OK;
 }
 

@@ -39,6 +39,7 @@ class Workload:
     precision: str
     note: str = ""
     extra_nrhs: tuple = dc_field(default_factory=tuple)
+    wavelengths: float = 0.0   # kappa > 0: b = -(2 pi kappa)^2 (Helmholtz), else b = 0
 
     @property
     def N(self) -> int:
@@ -69,6 +70,12 @@ WORKLOADS: Dict[str, Workload] = {
         "grf3d_n128", 3, 128, 4, 1e-3, "lognormal_grf", 256, 4, 40, "mixed",
         "3D log-normal coefficient, N=2097152, leaf 4^3, eps=1e-3",
         extra_nrhs=(1,)),
+    # Example 3: a = 1, b = -k^2 with k = 2 pi kappa, 32 unknowns per
+    # wavelength (kappa = 32 on the 1024^2 grid); indefinite, solved by GMRES
+    "helmholtz2d_n1024": Workload(
+        "helmholtz2d_n1024", 2, 1024, 16, 1e-6, "const", 16, None, 50, "mixed_elim64",
+        "2D Helmholtz, 32 wavelengths across the square, N=1048576, leaf 16x16",
+        wavelengths=32.0),
 }
 
 
@@ -136,6 +143,17 @@ def make_field(dim: int, n: int, field: str, seed: Optional[int]) -> List[np.nda
 
 def make_coefficients(w: Workload) -> List[np.ndarray]:
     return make_field(w.dim, w.n, w.field, w.seed_a)
+
+
+def helmholtz_b(N: int, wavelengths: float) -> np.ndarray:
+    """The constant ``b = -(2 pi kappa)^2`` of a Helmholtz problem with
+    ``kappa`` wavelengths across the unit square/cube."""
+    return np.full(N, -(2.0 * np.pi * wavelengths) ** 2)
+
+
+def make_b(w: Workload) -> Optional[np.ndarray]:
+    """``b`` of a workload, or None (b = 0)."""
+    return helmholtz_b(w.N, w.wavelengths) if w.wavelengths > 0 else None
 
 
 def make_rhs(N: int, nrhs: int, seed: int) -> np.ndarray:

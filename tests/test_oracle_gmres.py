@@ -1,5 +1,5 @@
 """Pins of the oracle's indefinite factorization (unpivoted LDL^T with
-negative pivots) and of its restarted GMRES (Section 6: indefinite problems
+negative pivots) and of its restarted GMRES (Section 5: indefinite problems
 with the factorization as preconditioner)."""
 import numpy as np
 import pytest
