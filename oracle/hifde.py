@@ -21,13 +21,19 @@ Free choices fixed here (listed with their reasons in the design notes):
   from ``A_l``, and a group whose rank equals its size is left alone.
 * ``eps = 0`` turns skeletonization off, which is the multifrontal method
   (Algorithm 3.1).
+* With ``sketch=True`` (the randomized compression of Section 4.3) a group
+  with ``|c^N| > |c| + 16`` takes the ID of ``Phi_c A_{c^N, c}``, ``Phi_c``
+  the ``(|c| + 16) x |c^N|`` Gaussian matrix of ``oracle.philox`` for the
+  group's level and key; the rank rule and tie-break are unchanged.
 
 Pinned by: eps=0 reproduces a sparse direct solve (tests/test_oracle_hifde.py),
 the block-diagonalizations of Lemmas 2.1 and 2.4 on random matrices, the ID
 against LAPACK's pivoted QR and exact low-rank reconstruction, symmetry and
 positive definiteness of F, the eigenvalue bound of Theorem 4.1's corollary,
 the partition of the unknowns, e_a = O(eps), and the flop count against
-closed-form sizes of the one-level tree.
+closed-form sizes of the one-level tree; the sketched ID by its invariance
+under orthogonal sketches, exact recovery of low-rank blocks and its error
+against the deterministic ID (tests/test_oracle_sketch.py).
 """
 from __future__ import annotations
 
@@ -38,7 +44,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from . import problem, tree
+from . import philox, problem, tree
 
 
 class NotSPD(RuntimeError):
@@ -271,12 +277,15 @@ def _add_blocks(A: sp.csr_matrix, blocks) -> sp.csr_matrix:
 # ---------------------------------------------------------------------------
 
 def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
-           skip_levels: int = 0, tau: float = 1e-10, definite: bool = True) -> Factor:
+           skip_levels: int = 0, tau: float = 1e-10, definite: bool = True,
+           sketch: bool = False) -> Factor:
     """HIF-DE factorization ``A ~= V_0^-T ... V_{L-1/2}^-T D V_{L-1/2}^-1 ... V_0^-1``.
 
     ``definite=False`` factors every diagonal block by the unpivoted
     ``ldl_sym`` (negative pivots allowed): F is then a congruence of the
-    block-diagonal D, symmetric but indefinite, for GMRES (Section 5)."""
+    block-diagonal D, symmetric but indefinite, for GMRES (Section 5).
+    ``sketch=True`` compresses ``Phi_c A_{c^N, c}`` instead of
+    ``A_{c^N, c}`` where ``|c^N| > |c| + 16`` (Section 4.3, randomized ID)."""
     if eps < 0 or eps >= 1:
         raise ValueError("eps must lie in [0, 1)")
     L = tree.num_levels(n, m)
@@ -310,6 +319,9 @@ def factor(dim: int, n: int, m: int, a, b=None, eps: float = 1e-6,
             do_skel = eps > 0 and lvl >= skip_levels
             if do_skel:
                 Mblk = _sub(A, cN, c)
+                rows = philox.sketch_rows(c.size, cN.size)
+                if sketch and rows < cN.size:
+                    Mblk = philox.sketch_matrix(lvl, int(gid), rows, cN.size) @ Mblk
                 idr = interp_decomp(Mblk, eps, tau)
                 k = idr.k
                 if k == c.size:
