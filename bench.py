@@ -156,9 +156,9 @@ def pmc_summary(fetch_dir, write_dir, workload):
         "# commands (from the repository root, TMPDIR=/tmp); the scales divide the known",
         "# size of a 4-byte-per-lane elementwise copy by what the counter reads for it",
         f"#   rocprofv3 --pmc FETCH_SIZE -f csv -d <FETCH_DIR> -- python bench.py --steps 1 "
-        f"--warmup 0 --no-cpu --no-fp64 --calib-copy",
+        f"--warmup 0 --no-cpu --no-fp64 --no-extra --calib-copy",
         f"#   rocprofv3 --pmc WRITE_SIZE -f csv -d <WRITE_DIR> -- python bench.py --steps 1 "
-        f"--warmup 0 --no-cpu --no-fp64 --calib-copy",
+        f"--warmup 0 --no-cpu --no-fp64 --no-extra --calib-copy",
         f"#   python bench.py --pmc-summary <FETCH_DIR> <WRITE_DIR>",
         f"kernel: {DOMINANT_KERNEL}",
         f"kernel_source_sha256: {source_sha(DOMINANT_SOURCE)}",
