@@ -333,11 +333,13 @@ def run_workload(H, torch, w, prec, nrhs_list, steps, warmup, profile_sweep):
     return out, t_total, prof
 
 
-def factor_roofline(stats, t_factor, mixed):
+def factor_roofline(stats, t_factor, cells_f32):
     """Algorithmic flops of the whole factorization over its time, against
-    the matrix cores' dense peak for the cells' and groups' type, and the
-    FP64 top block (|s_L|^3/3) over its device time against the FP64 peak."""
-    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    the matrix cores' dense peak for the cells' type (the cell eliminations
+    carry most of the flops: float under HIFDE_MIXED, double under FP64 and
+    MIXED_ELIM64), and the FP64 top block (|s_L|^3/3) over its device time
+    against the FP64 peak."""
+    peak = FP32_PEAK_TFLOPS if cells_f32 else FP64_PEAK_TFLOPS
     achieved = stats["factor_flops"] / t_factor / 1e12
     top = stats["top_size"]
     top_fl = top ** 3 / 3.0
@@ -590,7 +592,7 @@ def main():
     }
     out["roofline"] = sweep_roofline(prof, kernel,
                                      read_traffic(w.name) if kernel == DOMINANT_KERNEL else None)
-    out["factor_roofline"] = factor_roofline(stats, t_f, mixed)
+    out["factor_roofline"] = factor_roofline(stats, t_f, prec == H.HIFDE_MIXED)
     if not args.no_fp64 and prec == H.HIFDE_MIXED_ELIM64:
         # the all-float factorization, for comparison
         r32, _, _ = run_workload(H, torch, w, H.HIFDE_MIXED, [nrhs], 1, 1, False)
@@ -626,7 +628,8 @@ def main():
                     "eps": we.eps, "field": we.field, "precision": we.precision,
                     "solver": sv, "factor_ms": 1e3 * tfe, "factor_dof_per_s": we.N / tfe,
                     "top_size": r["stats"]["top_size"],
-                    "factor_roofline": factor_roofline(r["stats"], tfe, me), "solves": []}
+                    "factor_roofline": factor_roofline(r["stats"], tfe, pe_ == H.HIFDE_MIXED),
+                    "solves": []}
             if we.wavelengths > 0:
                 item["wavelengths"] = we.wavelengths
             for k in counts:

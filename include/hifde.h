@@ -88,12 +88,21 @@ enum {
                                    whole-front launches, interpolation as
                                    separate launches); the results are
                                    bitwise the same                         */
-  HIFDE_INDEFINITE = 256u       /* A may be indefinite (b < 0, Helmholtz-type
+  HIFDE_INDEFINITE = 256u,      /* A may be indefinite (b < 0, Helmholtz-type
                                    problems, Section 5): the LDL^T of every
                                    diagonal block accepts negative pivots
                                    (no pivoting; a zero or non-finite pivot
                                    fails with HIFDE_ENOTSPD).  Solve with
                                    hifde_gmres; hifde_pcg refuses the factor */
+  HIFDE_SKETCH_ID = 512u        /* randomized compression (Section 4.3): a
+                                   group with |c^N| > |c| + 16 takes the ID
+                                   of Phi A_{c^N,c}, Phi the (|c| + 16) x
+                                   |c^N| Gaussian matrix drawn from
+                                   Philox4x32-10 (key 0x9E3779B97F4A7C15,
+                                   counter (row, column, group key, level),
+                                   Box-Muller); same rank rule.  Fewer rows
+                                   for the pivoted QR, plus one product on
+                                   the matrix cores                        */
 };
 
 /* Maximum number of tree levels reported by hifde_stats. */

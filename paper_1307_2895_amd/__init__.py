@@ -14,7 +14,7 @@ import numpy as np
 from ._lib import (  # noqa: F401
     HIFDE_FP64, HIFDE_MIXED, HIFDE_MIXED_ELIM64, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH, HIFDE_USE_RANK_MODEL,
     HIFDE_AUTOTUNE,
-    HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES, HIFDE_INDEFINITE,
+    HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES, HIFDE_INDEFINITE, HIFDE_SKETCH_ID,
     HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE, HIFDE_ENOMEM,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,

@@ -22,6 +22,7 @@ HIFDE_USE_RANK_MODEL, HIFDE_DEBUG_DETERMINISM, HIFDE_AUTOTUNE, HIFDE_NO_GRAPH = 
 HIFDE_PRESIZE_WORST_CASE = 64
 HIFDE_SWEEP_ROW_TILES = 128
 HIFDE_INDEFINITE = 256
+HIFDE_SKETCH_ID = 512
 HIFDE_MAX_LEVELS = 24
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD",

@@ -90,4 +90,14 @@ struct GroupDev {
   int32_t skel;      // 1 if skeletonized
 };
 
+// A group whose ID runs on a Gaussian sketch Y = Phi M of its block
+// M = A_{c^N, c} (rows 0..nn-1 of its workspace, ld nn + nc).
+struct SketchDev {
+  int64_t m_off;     // M in the group workspace
+  int64_t phi_off;   // Phi (r x nn, ld r)
+  int64_t y_off;     // Y (r x nc, ld r + nc: the layout of a workspace with r rows)
+  int32_t nn, nc, r;
+  uint32_t gid;      // the group's key (the generator's counter)
+};
+
 }  // namespace hifde

@@ -517,6 +517,7 @@ struct hifde_factor_s {
   hifde_precision prec = HIFDE_FP64;
   double eps = 0.0;
   bool definite = true;        // without HIFDE_INDEFINITE: pivots must be positive
+  bool sketch = false;         // HIFDE_SKETCH_ID
   bool plan_only = false;
   std::unique_ptr<Planner> planner;
   std::vector<CellLevel> cl;   // L + 1 entries (last = top)
@@ -1103,6 +1104,7 @@ static PoolTable pools_for_level(const hifde_factor_s& F, int l_src) {
 // and restores the data for the real run.
 enum { FAM_LDL = 1, FAM_CPQR = 2, FAM_INV = 3 };
 constexpr int kCpqrWideFrom = 128;   // |c| from which the ID defaults to the wide form
+constexpr int kSketchOversample = 16;   // rows of a sketch beyond |c|
 constexpr int kAsmWideFrom = 512;    // front size from which extend-add goes wide
 static uint64_t tune_key(int fam, int esz, int a, int b, int c) {
   auto bucket = [](int v) {
@@ -1589,6 +1591,53 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   }
   HIP_CHECK(hipGetLastError());
   tm.mark("  gather", l);
+  // Randomized compression (Section 4.3): a group with |c^N| > |c| + 16 runs
+  // its ID on the sketch Y = Phi M of r = |c| + 16 rows; the others on a copy
+  // of M.  The IDs then read a workspace of their own, described by idh.
+  T* idw = static_cast<T*>(G.gw);
+  const GroupDev* idg = G.groups;
+  const std::vector<GroupDev>* idh = &G.gh;
+  size_t id_elems = size_t(S.gw_elems);
+  std::vector<GroupDev> sgh;
+  if (F.sketch) {
+    const auto& pg = P.level(l).groups();
+    std::vector<SketchDev> sk(G.ngroup);
+    sgh = G.gh;
+    int64_t yoff = 0, poff = 0, tiles = 1;
+    for (int g = 0; g < G.ngroup; ++g) {
+      const GroupDev& d = G.gh[g];
+      SketchDev& k = sk[g];
+      k.m_off = d.gw_off;
+      k.nn = d.nn;
+      k.nc = d.nc;
+      k.r = std::min<int>(d.nn, d.nc + kSketchOversample);
+      k.gid = uint32_t(pg[g].gid);
+      k.y_off = yoff;
+      if (k.r < k.nn) {
+        k.phi_off = poff;
+        poff += int64_t(k.r) * k.nn;
+      } else {
+        k.phi_off = -1;
+      }
+      yoff += (int64_t(k.r) + k.nc) * k.nc;
+      tiles = std::max<int64_t>(tiles, int64_t((k.r + 63) / 64) * ((k.nc + 63) / 64));
+      sgh[g].gw_off = k.y_off;
+      sgh[g].nn = k.r;
+    }
+    T* phi = F.mem.get<T>(size_t(std::max<int64_t>(poff, 1)));
+    idw = F.mem.get<T>(size_t(std::max<int64_t>(yoff, 1)));
+    id_elems = size_t(yoff);
+    const SketchDev* sk_d = F.mem.upload(sk, st);
+    idg = F.mem.upload(sgh, st);
+    idh = &sgh;
+    if (poff > 0)
+      hipLaunchKernelGGL(k_sketch_gen<T>, dim3(G.ngroup, 64), dim3(kThreads), 0, st, phi, sk_d,
+                         l);
+    hipLaunchKernelGGL(k_sketch_mfma<T>, dim3(G.ngroup, unsigned(tiles)), dim3(kThreads), 0, st,
+                       static_cast<const T*>(G.gw), static_cast<const T*>(phi), idw, sk_d);
+    HIP_CHECK(hipGetLastError());
+    tm.mark("  sketch", l);
+  }
   G.perm_stride = ncmax;
   G.kout = F.mem.get<int32_t>(G.ngroup);
   G.perm = F.mem.get<int32_t>(size_t(G.ngroup) * ncmax);
@@ -1608,9 +1657,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     std::vector<int32_t> order(G.ngroup);
     for (int g = 0; g < G.ngroup; ++g) order[g] = g;
     int nnmax = 0;
-    for (const GroupDev& d : G.gh) nnmax = std::max(nnmax, int(d.nn));
+    for (const GroupDev& d : *idh) nnmax = std::max(nnmax, int(d.nn));
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-      const GroupDev &a = G.gh[x], &b = G.gh[y];
+      const GroupDev &a = (*idh)[x], &b = (*idh)[y];
       return double(a.nn + a.nc) * a.nc * a.nc > double(b.nn + b.nc) * b.nc * b.nc;
     });
     const int32_t* order_d = F.mem.upload(order, st);
@@ -1625,8 +1674,8 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     int64_t ntot = 0;
     for (int g = 0; g < G.ngroup; ++g) {
       noff[g] = ntot;
-      ntot += G.gh[g].nc;
-      maxsteps = std::max(maxsteps, std::min<int>(G.gh[g].nn, G.gh[g].nc));
+      ntot += (*idh)[g].nc;
+      maxsteps = std::max(maxsteps, std::min<int>((*idh)[g].nn, (*idh)[g].nc));
     }
     auto run_wide = [&] {
       std::vector<int32_t> list(G.ngroup);
@@ -1645,14 +1694,14 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
         HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr_w_update<T>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(upd_lds)));
       hipLaunchKernelGGL(k_cpqr_w_init<T>, dim3(ng, chunks), dim3(kThreads), 0, st,
-                         static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, permw, stw);
+                         idw, idg, list_d, norms, noff_d, permw, stw);
       for (int j = 0; j < maxsteps; ++j) {
         hipLaunchKernelGGL(k_cpqr_w_pivot<T>, dim3(ng), dim3(kThreads), 0, st,
-                           static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, permw, stw, j,
+                           idw, idg, list_d, norms, noff_d, permw, stw, j,
                            F.eps, tau);
         const unsigned uch = unsigned(std::max(1, (ncmax - j - 1 + kCpqrChunk - 1) / kCpqrChunk));
         hipLaunchKernelGGL(k_cpqr_w_update<T>, dim3(ng, uch), dim3(kThreads), upd_lds, st,
-                           static_cast<T*>(G.gw), G.groups, list_d, norms, noff_d, stw, j);
+                           idw, idg, list_d, norms, noff_d, stw, j);
         if ((j & 31) == 31) {   // stop once every group has its rank
           int live = 0;
           hipLaunchKernelGGL(k_cpqr_w_live<T>, dim3(1), dim3(kThreads), 0, st, stw, G.ngroup,
@@ -1663,9 +1712,9 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
         }
       }
       hipLaunchKernelGGL(k_cpqr_w_tsolve<T>, dim3(ng, unsigned((ncmax + 63) / 64)), dim3(kThreads),
-                         0, st, static_cast<T*>(G.gw), G.groups, list_d, stw);
+                         0, st, idw, idg, list_d, stw);
       hipLaunchKernelGGL(k_cpqr_w_finish<T>, dim3(ng), dim3(kThreads), size_t(ncmax) * sizeof(int),
-                         st, static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, list_d,
+                         st, idw, static_cast<T*>(G.tpool), idg, list_d,
                          noff_d, permw, stw, G.kout, G.perm, G.perm_stride);
       HIP_CHECK(hipGetLastError());
     };
@@ -1676,7 +1725,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       }
       if (v == 3) {
         hipLaunchKernelGGL(k_cpqr_1k<T>, dim3(G.ngroup), dim3(1024), smem, st,
-                           static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, F.eps, tau,
+                           idw, static_cast<T*>(G.tpool), idg, F.eps, tau,
                            G.kout, G.perm, G.perm_stride);
         HIP_CHECK(hipGetLastError());
         return;
@@ -1684,11 +1733,11 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
       if (v == 1) {
         HIP_CHECK(hipMemsetAsync(counter, 0, sizeof(int), st));
         hipLaunchKernelGGL(k_cpqr_queue<T>, dim3(qgrid), dim3(kThreads), smem, st,
-                           static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, F.eps, tau,
+                           idw, static_cast<T*>(G.tpool), idg, F.eps, tau,
                            G.kout, G.perm, G.perm_stride, order_d, G.ngroup, counter);
       } else {
         hipLaunchKernelGGL(k_cpqr<T>, dim3(G.ngroup), dim3(kThreads), smem, st,
-                           static_cast<T*>(G.gw), static_cast<T*>(G.tpool), G.groups, F.eps, tau,
+                           idw, static_cast<T*>(G.tpool), idg, F.eps, tau,
                            G.kout, G.perm, G.perm_stride);
       }
       HIP_CHECK(hipGetLastError());
@@ -1696,7 +1745,7 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     // default: the wide form once groups are too large for one work-group
     const int dflt = ncmax >= kCpqrWideFrom ? 2 : G.ngroup < 256 ? 3 : 0;
     const int var = tune_choice(F, tune_key(FAM_CPQR, int(sizeof(T)), ncmax, nnmax, G.ngroup), 4,
-                                dflt, G.gw, size_t(S.gw_elems) * sizeof(T), st, run);
+                                dflt, idw, id_elems * sizeof(T), st, run);
     run(var);
   }
 
@@ -2849,7 +2898,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     return fail(HIFDE_EINVAL, "unknown precision");
   if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_AUTOTUNE |
                         HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE | HIFDE_SWEEP_ROW_TILES |
-                        HIFDE_INDEFINITE))
+                        HIFDE_INDEFINITE | HIFDE_SKETCH_ID))
     return fail(HIFDE_EINVAL, "unknown flags");
   if ((flags & HIFDE_USE_RANK_MODEL) && (flags & HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "HIFDE_USE_RANK_MODEL and HIFDE_PRESIZE_WORST_CASE exclude each other");
@@ -2866,6 +2915,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     F->model = presize == 1 ? tree->model_d.as<float>() : nullptr;
     F->autotune = (flags & HIFDE_AUTOTUNE) != 0;
     F->definite = !(flags & HIFDE_INDEFINITE);
+    F->sketch = (flags & HIFDE_SKETCH_ID) != 0;
     F->tree = tree;
     F->use_pool(tree->pool);
     build_factor(*F, tree, a, b, eps, prec, st);
@@ -2880,6 +2930,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
       F2.presize = presize;
       F2.model = F->model;
       F2.definite = F->definite;
+      F2.sketch = F->sketch;
       F2.tree = tree;
       build_factor(F2, tree, a, b, eps, prec, st);
       compare_factors(*F, F2, st);
