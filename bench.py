@@ -278,7 +278,7 @@ def run_workload(H, torch, w, prec, nrhs_list, steps, warmup, profile_sweep):
     b_h = W.make_b(w)
     b_d = None if b_h is None else torch.from_numpy(b_h).to(dev)
     indefinite = b_h is not None
-    flags = H.HIFDE_INDEFINITE if indefinite else 0
+    flags = (H.HIFDE_INDEFINITE if indefinite else 0) | (H.HIFDE_SKETCH_ID if w.sketch else 0)
     f_d = {k: torch.from_numpy(W.make_rhs(N, k, w.seed_f)).to(dev) for k in nrhs_list}
     tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
     prof = {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0}
@@ -520,7 +520,7 @@ def main():
         a_d = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in W.make_coefficients(w)]
         b_h = W.make_b(w)
         b_d = None if b_h is None else torch.from_numpy(b_h).cuda()
-        fl = 0 if b_h is None else H.HIFDE_INDEFINITE
+        fl = (0 if b_h is None else H.HIFDE_INDEFINITE) | (H.HIFDE_SKETCH_ID if w.sketch else 0)
         tree = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
         prec = H.PRECISIONS[w.precision]
         for i in range(args.warmup + args.steps):
@@ -626,7 +626,7 @@ def main():
             sv = "gmres" if we.wavelengths > 0 else "pcg"
             item = {"workload": name, "dim": we.dim, "n": we.n, "N": we.N, "leaf": we.leaf,
                     "eps": we.eps, "field": we.field, "precision": we.precision,
-                    "solver": sv, "factor_ms": 1e3 * tfe, "factor_dof_per_s": we.N / tfe,
+                    "randomized_id": we.sketch, "solver": sv, "factor_ms": 1e3 * tfe, "factor_dof_per_s": we.N / tfe,
                     "top_size": r["stats"]["top_size"],
                     "factor_roofline": factor_roofline(r["stats"], tfe, pe_ == H.HIFDE_MIXED),
                     "solves": []}

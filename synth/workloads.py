@@ -40,6 +40,7 @@ class Workload:
     note: str = ""
     extra_nrhs: tuple = dc_field(default_factory=tuple)
     wavelengths: float = 0.0   # kappa > 0: b = -(2 pi kappa)^2 (Helmholtz), else b = 0
+    sketch: bool = False       # randomized ID (Gaussian sketch of each tall group block)
 
     @property
     def N(self) -> int:
@@ -65,11 +66,11 @@ WORKLOADS: Dict[str, Workload] = {
         "mixed_elim64", "2D high-contrast (1e4) field, N=1048576, leaf 16x16"),
     "laplace3d_n64": Workload(
         "laplace3d_n64", 3, 64, 4, 1e-6, "const", 64, None, 30, "mixed",
-        "3D seven-point Laplacian, N=262144, leaf 4^3"),
+        "3D seven-point Laplacian, N=262144, leaf 4^3", sketch=True),
     "grf3d_n128": Workload(
         "grf3d_n128", 3, 128, 4, 1e-3, "lognormal_grf", 256, 4, 40, "mixed",
         "3D log-normal coefficient, N=2097152, leaf 4^3, eps=1e-3",
-        extra_nrhs=(1,)),
+        extra_nrhs=(1,), sketch=True),
     # Example 3: a = 1, b = -k^2 with k = 2 pi kappa, 32 unknowns per
     # wavelength (kappa = 32 on the 1024^2 grid); indefinite, solved by GMRES
     "helmholtz2d_n1024": Workload(

@@ -1,6 +1,6 @@
 """GPU parity at the full workload sizes, in the configuration bench.py
-times (default flags: captured F^-1 graphs, mixed precision where the
-workload says so).
+times (captured F^-1 graphs; mixed precision and the randomized ID where
+the workload says so).
 
 The oracle cannot factor these sizes in test time, so the checks are what it
 can compute independently at any size:
@@ -89,7 +89,8 @@ def test_full_size(name, nrhs):
     a = W.make_coefficients(w)
     T = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
     prec = H.PRECISIONS[w.precision]
-    F = H.hifde_factor(T, torch_inputs(a), None, w.eps, prec)
+    F = H.hifde_factor(T, torch_inputs(a), None, w.eps, prec,
+                       flags=H.HIFDE_SKETCH_ID if w.sketch else 0)
     _check_tree(F, w)
     f = W.make_rhs(w.N, nrhs, w.seed_f)
     u, its, rel = H.hifde_pcg(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=200)
