@@ -94,7 +94,7 @@ enum {
                                    (no pivoting; a zero or non-finite pivot
                                    fails with HIFDE_ENOTSPD).  Solve with
                                    hifde_gmres; hifde_pcg refuses the factor */
-  HIFDE_SKETCH_ID = 512u        /* randomized compression (Section 4.3): a
+  HIFDE_SKETCH_ID = 512u,       /* randomized compression (Section 4.3): a
                                    group with |c^N| > |c| + 16 takes the ID
                                    of Phi A_{c^N,c}, Phi the (|c| + 16) x
                                    |c^N| Gaussian matrix drawn from
@@ -103,6 +103,14 @@ enum {
                                    Box-Muller); same rank rule.  Fewer rows
                                    for the pivoted QR, plus one product on
                                    the matrix cores                        */
+  HIFDE_RETRY_FP64 = 1024u      /* a float factorization (HIFDE_MIXED or
+                                   HIFDE_MIXED_ELIM64) that fails on a pivot
+                                   is done again in double (HIFDE_FP64):
+                                   rounding in float can turn a small
+                                   positive eigenvalue of a Schur complement
+                                   negative.  hifde_stats reports the
+                                   precision used and the retry.  A failure
+                                   in double is reported as usual          */
 };
 
 /* Maximum number of tree levels reported by hifde_stats. */
@@ -134,6 +142,8 @@ typedef struct {
                                        has queued the level's work)          */
   double top_ms;                    /* device time of the top block (level L:
                                        assembly, LDL^T in double, apply form) */
+  int32_t precision;                /* hifde_precision the factor holds      */
+  int32_t retried;                  /* 1: HIFDE_RETRY_FP64 redid it in double */
 } hifde_stats_t;
 
 /* Index sets of one (fractional) level, for comparison with other

@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     HIFDE_FP64, HIFDE_MIXED, HIFDE_MIXED_ELIM64, HIFDE_DEBUG_DETERMINISM, HIFDE_NO_GRAPH, HIFDE_USE_RANK_MODEL,
     HIFDE_AUTOTUNE,
     HIFDE_PRESIZE_WORST_CASE, HIFDE_SWEEP_ROW_TILES, HIFDE_INDEFINITE, HIFDE_SKETCH_ID,
+    HIFDE_RETRY_FP64,
     HifdeError, Prof, Sets, Stats, check, lib,
     HIFDE_ENOCONV, HIFDE_EINVAL, HIFDE_ENOTSPD, HIFDE_ESTATE, HIFDE_ENOMEM,
     HIFDE_PROF_SWEEP_UP, HIFDE_PROF_SWEEP_DOWN, HIFDE_PROF_INTERP, HIFDE_PROF_TOP,
@@ -186,6 +187,7 @@ def hifde_stats(F: Factor) -> dict:
         "rank_groups": s.rank_groups, "rank_mae": s.rank_mae, "rebuckets": s.rebuckets,
         "skel_panels": s.skel_panels, "tuned": s.tuned,
         "level_ms": list(s.level_ms[:L]), "top_ms": s.top_ms,
+        "precision": s.precision, "retried": bool(s.retried),
     }
 
 

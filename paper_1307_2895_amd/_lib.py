@@ -23,6 +23,7 @@ HIFDE_PRESIZE_WORST_CASE = 64
 HIFDE_SWEEP_ROW_TILES = 128
 HIFDE_INDEFINITE = 256
 HIFDE_SKETCH_ID = 512
+HIFDE_RETRY_FP64 = 1024
 HIFDE_MAX_LEVELS = 24
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD",
@@ -75,6 +76,8 @@ class Stats(C.Structure):
         ("tuned", C.c_int64),
         ("level_ms", C.c_double * HIFDE_MAX_LEVELS),
         ("top_ms", C.c_double),
+        ("precision", C.c_int32),
+        ("retried", C.c_int32),
     ]
 
 

@@ -1983,6 +1983,7 @@ static bool float_sweeps(const hifde_factor_s& F) { return F.prec != HIFDE_FP64;
 static void fill_stats(hifde_factor_s& F) {
   hifde_stats_t& s = F.stats;
   const Planner& P = *F.planner;
+  s.precision = int32_t(F.prec);
   s.N = F.g.N;
   s.dim = F.g.dim;
   s.levels = F.g.L;
@@ -2898,7 +2899,7 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
     return fail(HIFDE_EINVAL, "unknown precision");
   if (flags & ~uint32_t(HIFDE_USE_RANK_MODEL | HIFDE_DEBUG_DETERMINISM | HIFDE_AUTOTUNE |
                         HIFDE_NO_GRAPH | HIFDE_PRESIZE_WORST_CASE | HIFDE_SWEEP_ROW_TILES |
-                        HIFDE_INDEFINITE | HIFDE_SKETCH_ID))
+                        HIFDE_INDEFINITE | HIFDE_SKETCH_ID | HIFDE_RETRY_FP64))
     return fail(HIFDE_EINVAL, "unknown flags");
   if ((flags & HIFDE_USE_RANK_MODEL) && (flags & HIFDE_PRESIZE_WORST_CASE))
     return fail(HIFDE_EINVAL, "HIFDE_USE_RANK_MODEL and HIFDE_PRESIZE_WORST_CASE exclude each other");
@@ -2911,17 +2912,33 @@ int hifde_factor(hifde_tree_t tree, const double* const* a, const double* b, dou
   int rc = guarded([&] {
     auto t0 = std::chrono::steady_clock::now();
     const int presize = (flags & HIFDE_USE_RANK_MODEL) ? 1 : (flags & HIFDE_PRESIZE_WORST_CASE) ? 2 : 0;
-    F->presize = presize;
-    F->model = presize == 1 ? tree->model_d.as<float>() : nullptr;
-    F->autotune = (flags & HIFDE_AUTOTUNE) != 0;
-    F->definite = !(flags & HIFDE_INDEFINITE);
-    F->sketch = (flags & HIFDE_SKETCH_ID) != 0;
-    F->tree = tree;
-    F->use_pool(tree->pool);
-    build_factor(*F, tree, a, b, eps, prec, st);
+    auto setup = [&](hifde_factor_s& G) {
+      G.presize = presize;
+      G.model = presize == 1 ? tree->model_d.as<float>() : nullptr;
+      G.autotune = (flags & HIFDE_AUTOTUNE) != 0;
+      G.definite = !(flags & HIFDE_INDEFINITE);
+      G.sketch = (flags & HIFDE_SKETCH_ID) != 0;
+      G.tree = tree;
+      G.use_pool(tree->pool);
+    };
+    setup(*F);
+    bool retried = false;
+    try {
+      build_factor(*F, tree, a, b, eps, prec, st);
+    } catch (const Error& e) {
+      // a pivot of the float factorization failed: factor again in double
+      if (!(flags & HIFDE_RETRY_FP64) || e.code != HIFDE_ENOTSPD || prec == HIFDE_FP64) throw;
+      HIP_CHECK(hipStreamSynchronize(st));
+      F.reset(new hifde_factor_s);
+      setup(*F);
+      prec = HIFDE_FP64;
+      retried = true;
+      build_factor(*F, tree, a, b, eps, prec, st);
+    }
     F->use_graph = !(flags & HIFDE_NO_GRAPH);
     F->row_tiles = (flags & HIFDE_SWEEP_ROW_TILES) != 0;
     fill_stats(*F);
+    F->stats.retried = retried ? 1 : 0;
     F->stats.factor_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (flags & HIFDE_DEBUG_DETERMINISM) {

@@ -1,7 +1,8 @@
 """Failure paths of the C ABI on the GPU: a matrix that is not positive
 definite (ENOTSPD, naming the level of the failing block), PCG that misses
-its tolerance (ENOCONV with iters, relres and the last iterate filled), and
-a device-memory cap (ENOMEM).  After each failure the tree still factors a
+its tolerance (ENOCONV with iters, relres and the last iterate filled), a
+device-memory cap (ENOMEM), and a float pivot failure redone in double
+(HIFDE_RETRY_FP64).  After each failure the tree still factors a
 valid problem.  Every failure is forced by the inputs or the host: no kernel
 faults or hangs."""
 import numpy as np
@@ -94,3 +95,40 @@ def test_memory_limit_gives_enomem_and_tree_recovers():
     assert ei.value.code == H.HIFDE_EINVAL
     H.hifde_tree_set_memory_limit(T, 0)
     _tree_still_works(T, a, W.make_rhs(n * n, 2, 5))
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_float_pivot_failure_is_retried_in_double(prec):
+    """b = -lambda_min(L) + 1e-6 on the 64^2 grid: A is positive definite
+    with smallest eigenvalue 1e-6 (closed form) against ||A|| of about
+    3.4e4.  Rounding the Schur complements to float (about 1e-7 relative,
+    i.e. 3e-3 absolute) turns a pivot negative; in double it stays positive.
+    Without the flag the float factorization fails with ENOTSPD; with
+    HIFDE_RETRY_FP64 it is redone in double and equals, bit for bit, the
+    factorization requested in double."""
+    import paper_1307_2895_amd as H
+    n, m = 64, 8
+    h = 1.0 / (n + 1)
+    lam_min = 8 / h ** 2 * np.sin(np.pi * h / 2) ** 2
+    a = W.make_field(2, n, "const", None)
+    b = torch.full((n * n,), -lam_min + 1e-6, dtype=torch.float64).cuda()
+    print(f"case retry prec={prec}", flush=True)
+    T = H.hifde_build_tree(2, n, m, 0)
+    with pytest.raises(H.HifdeError) as ei:
+        H.hifde_factor(T, torch_inputs(a), b, 0.0, prec)
+    assert ei.value.code == H.HIFDE_ENOTSPD
+    F = H.hifde_factor(T, torch_inputs(a), b, 0.0, prec, flags=H.HIFDE_RETRY_FP64)
+    st = H.hifde_stats(F)
+    assert st["precision"] == H.HIFDE_FP64 and st["retried"]
+    F64 = H.hifde_factor(T, torch_inputs(a), b, 0.0, H.HIFDE_FP64)
+    s64 = H.hifde_stats(F64)
+    assert s64["precision"] == H.HIFDE_FP64 and not s64["retried"]
+    f = torch.from_numpy(W.make_rhs(n * n, 2, 13)).cuda()
+    assert torch.equal(H.hifde_solve(F, f), H.hifde_solve(F64, f))
+    F.free()
+    F64.free()
+    # a factorization that succeeds in float is not redone
+    F = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec, flags=H.HIFDE_RETRY_FP64)
+    st = H.hifde_stats(F)
+    assert st["precision"] == prec and not st["retried"]
+    F.free()
