@@ -4,11 +4,15 @@ Follows the five-point (2D, Section 3.1) and seven-point (3D, Section 3.2)
 finite-difference stencils with the coefficient ``a`` sampled on the
 staggered links and ``b`` at the nodes, homogeneous Dirichlet boundary
 conditions, and ``h = 1/(n+1)`` for ``n`` unknowns per side (the paper writes
-``N = (n-1)^d`` with ``h = 1/n``; here ``n`` counts unknowns).
+``N = (n-1)^d`` with ``h = 1/n``; here ``n`` counts unknowns).  A zero
+coefficient on the boundary links of a side drops their Dirichlet term and
+makes that side zero-flux (Neumann, first order): mixed boundary conditions
+(Section 6) without a change of stencil.
 
 Pinned by: the DST-I closed-form eigen-decomposition of the constant
 coefficient Laplacian (tests/test_oracle_problem.py), brute-force assembly
-at n <= 4, and symmetry.
+at n <= 4, symmetry, and the closed-form spectrum of a grid with one
+zero-flux side.
 """
 from __future__ import annotations
 

@@ -1,10 +1,14 @@
 """Cells, separators and skeletonization groups of the uniform tree.
 
 Geometry (Sections 3.1, 4.1, 4.2): at level l the domain is cut into boxes of
-``M_l = m 2^l`` unknowns per side.  With ``n`` unknowns per side (``n/m`` a
-power of two, at least 2) the separators are the last row of every box but
-the last along each axis: coordinate ``x_k`` lies on a level-l separator iff
-``(x_k + 1) mod M_l == 0`` and ``x_k != n-1``.
+``M_l = m 2^l`` unknowns per side, ``B_l = ceil(n / M_l)`` of them along each
+axis; the last box along an axis is shorter when ``M_l`` does not divide
+``n`` (any ``n`` with at least two leaf boxes per side; ``n = m 2^L`` gives
+the uniform tree of the paper's figures, ``n = 2^k - 1`` its example grids).
+The separators are the last row of every box but the last along each axis:
+coordinate ``x_k`` lies on a level-l separator iff ``(x_k + 1) mod M_l == 0``
+and ``x_k != n-1``.  The top level L is the first with a single box
+(``m 2^L >= n``).
 
 * ``sigma_l(i)`` counts the axes on which unknown ``i`` lies on a level-l
   separator.
@@ -24,13 +28,20 @@ from __future__ import annotations
 import numpy as np
 
 
+def boxes(n: int, M: int) -> int:
+    """Boxes of side M along an axis of n unknowns (the last may be short)."""
+    return -(-n // M)
+
+
 def num_levels(n: int, m: int) -> int:
-    if m < 2 or n % m != 0:
-        raise ValueError("leaf size must be >= 2 and divide n")
-    B0 = n // m
-    L = int(round(np.log2(B0)))
-    if B0 < 2 or (1 << L) != B0:
-        raise ValueError("n/leaf must be a power of two >= 2")
+    if m < 2:
+        raise ValueError("leaf size must be >= 2")
+    B0 = boxes(n, m)
+    if B0 < 2:
+        raise ValueError("n must hold at least two leaf boxes per side")
+    L = 0
+    while (1 << L) < B0:
+        L += 1
     return L
 
 
@@ -46,7 +57,7 @@ def sigma(coords: np.ndarray, n: int, M: int) -> np.ndarray:
 
 def box_id(coords: np.ndarray, n: int, M: int) -> np.ndarray:
     """Lexicographic box index (x0 fastest) of each unknown at box side M."""
-    B = n // M
+    B = boxes(n, M)
     bx = coords // M
     out = np.zeros(coords.shape[0], dtype=np.int64)
     for k in range(coords.shape[1]):
@@ -58,7 +69,7 @@ def group_id(coords: np.ndarray, n: int, M: int) -> np.ndarray:
     """Key of the group holding each sigma=1 unknown:
     ``k * B^d + lexicographic(box indices with box_k := plane index)``."""
     dim = coords.shape[1]
-    B = n // M
+    B = boxes(n, M)
     s = sep_axis(n, M)[coords]                     # (N, dim) bool
     k = np.argmax(s, axis=1)
     bx = coords // M

@@ -61,3 +61,21 @@ def test_coefficient_layout():
         for k in range(dim):
             s = W.coeff_shape(dim, 5, k)
             assert s[dim - 1 - k] == 6 and sum(s) == 5 * dim + 1
+
+
+def test_zero_boundary_links_give_neumann_sides():
+    """A zero coefficient on the boundary links of the x0 = 0 side removes
+    their Dirichlet term (a zero-flux side, first order): along x0 the
+    matrix is h^-2 tridiag(-1, 2, -1) with first entry 1, whose eigenvalues
+    are 2 - 2 cos((2j - 1) pi / (2n + 1)); A is the Kronecker sum with the
+    Dirichlet axis, 2 - 2 cos(j pi / (n + 1))."""
+    n = 12
+    a = [np.ones((n, n + 1)), np.ones((n + 1, n))]
+    a[0][:, 0] = 0.0                     # links 0 along axis 0 (x0 = 0 side)
+    A = problem.assemble(2, n, a)
+    j = np.arange(1, n + 1)
+    lam_n = 2 - 2 * np.cos((2 * j - 1) * np.pi / (2 * n + 1))
+    lam_d = 2 - 2 * np.cos(j * np.pi / (n + 1))
+    want = np.sort((lam_n[:, None] + lam_d[None, :]).ravel()) * (n + 1) ** 2
+    got = np.linalg.eigvalsh(A.toarray())
+    np.testing.assert_allclose(got, want, rtol=1e-10)

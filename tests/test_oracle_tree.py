@@ -68,3 +68,45 @@ def test_corners_never_grouped():
             grouped[c] = True
         assert not np.any(grouped & (sig >= 2))
         assert np.all(grouped[active & (sig == 1)])
+
+
+# Grids whose side is not m 2^L: the last box along each axis is short.
+RAGGED = [(2, 60, 8), (2, 65, 8), (3, 30, 4), (2, 1023, 16)]
+
+
+@pytest.mark.parametrize("dim,n,m", RAGGED)
+def test_ragged_counts(dim, n, m):
+    """B_l = ceil(n / (m 2^l)) boxes per axis; each box keeps its non-separator
+    coordinates (n - (B_0 - 1) per axis in all), the level-1/2 groups are the
+    (B_0 - 1) separator planes times the boxes of the other axes, and the
+    top level L is the first with one box."""
+    L = tree.num_levels(n, m)
+    B0 = -(-n // m)
+    assert (m << (L - 1)) < n <= (m << L)
+    X = problem.dof_coords(dim, n)
+    active = np.ones(n ** dim, dtype=bool)
+    cells = tree.cells_at_level(X, active, n, m, 0)
+    assert len(cells) == B0 ** dim
+    assert sum(len(p) for _, p in cells) == (n - (B0 - 1)) ** dim
+    for _, p in cells:
+        active[p] = False
+    groups = tree.groups_at_level(X, active, n, m, 0)
+    if dim == 2:
+        assert len(groups) == 2 * B0 * (B0 - 1)
+    else:
+        assert len(groups) == 3 * (B0 - 1) * B0 ** 2
+    assert not np.any(tree.sep_axis(n, m << L))
+
+
+@pytest.mark.parametrize("dim,n,m,eps", [(2, 60, 8, 1e-6), (2, 65, 8, 1e-3), (3, 30, 4, 1e-6)])
+def test_ragged_partition_and_exact_solve(dim, n, m, eps):
+    """Every unknown is eliminated once on ragged grids, and at eps = 0 the
+    factorization is a sparse direct solve."""
+    import scipy.sparse.linalg as spla
+    a = W.make_field(dim, n, "loguniform", 9)
+    F = OH.factor(dim, n, m, a, eps=eps)
+    assert OH.partition_sizes(F) == n ** dim
+    F0 = OH.factor(dim, n, m, a, eps=0.0)
+    f = W.make_rhs(n ** dim, 1, 4)[:, 0]
+    ud = spla.spsolve(F0.A.tocsc(), f)
+    assert np.linalg.norm(OH.solve(F0, f) - ud) <= 1e-11 * np.linalg.norm(ud)
