@@ -160,14 +160,18 @@ typedef struct {
   int32_t* lists[4];  /* concatenated lists (host, caller-owned)             */
 } hifde_sets_t;
 
-/* Build the uniform tree of Sections 3.1-3.2 and 4.1-4.2: n unknowns per side,
- * leaf boxes of `leaf` unknowns per side, L = log2(n/leaf) levels.  The first
+/* Build the tree of Sections 3.1-3.2 and 4.1-4.2: n unknowns per side, boxes
+ * of leaf * 2^l unknowns per side at level l, L = log2(ceil(n/leaf)) levels,
+ * the top one a single box.  When leaf does not divide n the last box along
+ * each axis is shorter (e.g. the paper's n = 2^k - 1 grids); the number of
+ * leaf boxes per side, ceil(n/leaf), must be a power of two (otherwise a
+ * short corner box could be left with nothing to eliminate).  The first
  * `skip_levels` fractional levels are not skeletonized (Section 5).
  * Host-only; no device work.  The tree also keeps, for reuse by its later
  * factorizations, the device memory of factorizations that were freed; it
  * is released when the tree and all its factorizations are freed (or, when
  * a device allocation fails, before it is retried).
- * EINVAL: dim not 2 or 3, leaf < 2, n/leaf not a power of two >= 2,
+ * EINVAL: dim not 2 or 3, leaf < 2, ceil(n/leaf) not a power of two >= 2,
  * skip_levels < 0, N >= 2^31. */
 int hifde_build_tree(int dim, int64_t n, int64_t leaf, int skip_levels,
                      hifde_tree_t* out);
@@ -188,8 +192,11 @@ int hifde_tree_set_memory_limit(hifde_tree_t tree, int64_t bytes);
  * relative ID tolerance of Section 2.2; eps = 0 disables skeletonization
  * (the multifrontal method, Algorithm 3.1).  The returned factor keeps no
  * reference to a or b.
- * EINVAL: eps outside [0, 1), NULL a[k], non-positive or non-finite a
- * (checked on the device), non-finite b.  ENOTSPD: a pivot of a diagonal
+ * A zero coefficient on boundary links (link 0 or n along an axis) makes
+ * that part of the boundary zero-flux (Neumann) rather than Dirichlet.
+ * EINVAL: eps outside [0, 1), NULL a[k], a not positive on an interior link,
+ * negative on a boundary link or not finite (checked on the device),
+ * non-finite b.  ENOTSPD: a pivot of a diagonal
  * block was not positive (with HIFDE_INDEFINITE: was zero or not finite);
  * hifde_last_error() names the level and block.
  * The pivots of each level are read with that level's skeleton ranks, so

@@ -1285,7 +1285,8 @@ static void check_input(hifde_factor_s& F, hipStream_t st) {
   HIP_CHECK(hipMemcpyAsync(&h, F.bad_d, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   F.input_checked = true;
-  if (h & 1) throw Error(HIFDE_EINVAL, "a must be positive and finite");
+  if (h & 1)
+    throw Error(HIFDE_EINVAL, "a must be finite, positive on interior links, >= 0 on boundary links");
   if (h & 2) throw Error(HIFDE_EINVAL, "b must be finite");
 }
 

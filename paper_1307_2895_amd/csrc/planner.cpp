@@ -262,9 +262,11 @@ static void bucket_by_key(const std::vector<int32_t>& key, int64_t nkey, int wor
 std::string check_geom(int dim, int64_t n, int64_t leaf, int skip, Geom* out) {
   if (dim != 2 && dim != 3) return "dim must be 2 or 3";
   if (leaf < 2) return "leaf must be at least 2";
-  if (n < 4 || n % leaf != 0) return "leaf must divide n";
-  int64_t B = n / leaf;
-  if (B < 2 || (B & (B - 1)) != 0) return "n/leaf must be a power of two >= 2";
+  if (n <= leaf) return "n must hold at least two leaf boxes per side";
+  // ceil(n/leaf) leaf boxes per side, the last one possibly short: a power
+  // of two, so that every box of every level keeps unknowns to eliminate
+  const int64_t B = (n + leaf - 1) / leaf;
+  if ((B & (B - 1)) != 0) return "ceil(n/leaf) must be a power of two";
   if (skip < 0) return "skip_levels must be >= 0";
   int64_t N = 1;
   for (int k = 0; k < dim; ++k) N *= n;
@@ -373,7 +375,7 @@ int64_t Planner::box_of(int64_t d, int l) const {
   if (l >= g_.L) return 0;
   int64_t x[3];
   coords(d, x);
-  const int64_t M = g_.m << l, B = g_.n / M;
+  const int64_t M = g_.m << l, B = (g_.n + M - 1) / M;
   int64_t id = 0, mul = 1;
   for (int k = 0; k < g_.dim; ++k) {
     id += (x[k] / M) * mul;
@@ -386,7 +388,7 @@ int64_t Planner::box_of(int64_t d, int l) const {
 int64_t Planner::group_key(int64_t d, int l) const {
   int64_t x[3];
   coords(d, x);
-  const int64_t M = g_.m << l, B = g_.n / M;
+  const int64_t M = g_.m << l, B = (g_.n + M - 1) / M;
   int64_t id = 0, mul = 1;
   int axis = 0;
   for (int k = 0; k < g_.dim; ++k) {
@@ -503,7 +505,7 @@ void Planner::plan_cells(int l) {
 void Planner::build_cells(int l, LevelPlan& lp) {
   PlanTimer tm("cells", l);
   const bool top = (l == g_.L);
-  const int64_t B = top ? 1 : g_.n / (g_.m << l);
+  const int64_t B = top ? 1 : boxes_per_axis(g_, l);
   int64_t nbox = 1;
   for (int k = 0; k < g_.dim; ++k) nbox *= B;
   const auto interior = [&](int64_t d) { return top || sigma(d, l) == 0; };
@@ -545,7 +547,7 @@ void Planner::build_cells(int l, LevelPlan& lp) {
   std::vector<std::vector<int32_t>> kids(lp.cells.size()), gkids(lp.cells.size());
   if (l > 0) {
     const Level& prev = lv_[l - 1];
-    const int64_t Bp = g_.n / (g_.m << (l - 1));
+    const int64_t Bp = boxes_per_axis(g_, l - 1);
     // parents found in parallel, lists filled in order
     std::vector<int32_t> kpar(prev.cells().size()), gpar(prev.groups().size(), -1);
     parallel_for(kpar.size(), 256, workers_, [&](size_t ci, int) {
@@ -671,7 +673,7 @@ void Planner::plan_groups(int l) {
 
 void Planner::build_groups(int l, LevelPlan& lp) {
   PlanTimer tm("groups", l);
-  const int64_t B = g_.n / (g_.m << l);
+  const int64_t B = boxes_per_axis(g_, l);
   int64_t nkey = g_.dim;
   for (int k = 0; k < g_.dim; ++k) nkey *= B;
   std::vector<int32_t> keyv(act_.size());

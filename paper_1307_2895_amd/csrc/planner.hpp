@@ -38,6 +38,13 @@ struct Geom {
   int64_t stride[3] = {1, 1, 1};
 };
 
+// Boxes of side m 2^l along an axis (the last one is short when m 2^l does
+// not divide n).
+inline int64_t boxes_per_axis(const Geom& g, int l) {
+  const int64_t M = g.m << l;
+  return (g.n + M - 1) / M;
+}
+
 // A stencil value: diagonal of unknown d (ref = d) or the link between d and
 // d + stride[k] (ref = N * (1 + k) + d).
 struct Trip {

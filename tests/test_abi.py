@@ -38,8 +38,9 @@ def test_library_exports_every_declared_function():
 @pytest.mark.parametrize("dim,n,leaf,skip", [
     (4, 64, 8, 0),     # dim not 2 or 3
     (2, 64, 1, 0),     # leaf < 2
-    (2, 48, 8, 0),     # n/leaf = 6 not a power of two
-    (2, 8, 8, 0),      # n/leaf = 1
+    (2, 8, 8, 0),      # one leaf box per side
+    (2, 5, 8, 0),      # n below the leaf size
+    (2, 65, 8, 0),     # ceil(n/leaf) = 9 not a power of two
     (2, 64, 8, -1),    # negative skip
     (3, 2048, 8, 0),   # N >= 2^31
 ])
@@ -98,6 +99,10 @@ REPLAY_CASES = [
     (2, 32, 4, 0.0, "const", None, 0),
     (3, 16, 4, 1e-6, "const", None, 0),
     (3, 16, 2, 1e-3, "lognormal_grf", 4, 0),
+    # ragged grids: the last box along each axis is short
+    (2, 60, 8, 1e-6, "loguniform", 7, 0),
+    (2, 57, 8, 1e-3, "bernoulli_contrast", 2, 0),   # last leaf box one wide
+    (3, 30, 4, 1e-6, "const", None, 0),
 ]
 
 
