@@ -864,7 +864,10 @@ static unsigned active_fronts(const std::vector<FrontDev>& fh, int j, bool sorte
 }
 
 // Trailing-update variants of the batched LDL^T.
-enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_VARIANTS = 2 };
+enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_FRONT = 2, LDL_VARIANTS = 3 };
+// Variants the tuner times for a launch of nf fronts: the one-launch form
+// (one work-group per front) only when the fronts fill the device.
+static inline int ldl_timed(int64_t nf) { return nf >= 256 ? LDL_VARIANTS : LDL_FRONT; }
 
 // With `bounds`, the p of fh are upper bounds of the device fronts' pivot
 // counts (the device holds the exact ones); launch shapes then cover any
@@ -873,8 +876,30 @@ enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_VARIANTS = 2 };
 template <typename T>
 static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
                         int* info_d, int definite, hipStream_t st, bool bounds = false,
-                        bool sorted = false, int variant = LDL_MFMA) {
+                        bool sorted = false, int variant = LDL_MFMA, int* counter = nullptr) {
   if (fh.empty()) return;
+  if (variant == LDL_FRONT && counter) {
+    // one persistent launch: a full round of the device, fronts from a queue
+    static const std::pair<int, int> occ = [] {
+      int dev = 0, cus = 0, per_cu = 0;
+      HIP_CHECK(hipGetDevice(&dev));
+      HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_ldl_front<T>), kThreads, 0));
+      return std::make_pair(per_cu, cus);
+    }();
+    const int per_cu = occ.first, cus = occ.second;
+    const int64_t nf = int64_t(fh.size());
+    const unsigned grid =
+        unsigned(std::max<int64_t>(1, std::min<int64_t>(nf, int64_t(std::max(1, per_cu)) *
+                                                                std::max(1, cus))));
+    HIP_CHECK(hipMemsetAsync(counter, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_ldl_front<T>, dim3(grid), dim3(kThreads), 0, st, pool, fronts_d, int(nf),
+                       info_d, definite, counter);
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+  if (variant == LDL_FRONT) variant = LDL_MFMA;
   int pmax = 0;
   for (const auto& f : fh) pmax = std::max(pmax, f.p);
   // Tiles of an update whose trailing block starts `w` columns after j0
@@ -1129,9 +1154,11 @@ static int forced_variant(int fam) {
 
 template <class Run>
 static int tune_choice(hifde_factor_s& F, uint64_t key, int nvar, int dflt, void* buf,
-                       size_t bytes, hipStream_t st, Run run) {
+                       size_t bytes, hipStream_t st, Run run, int ntime = -1) {
+  // ntime: only variants below it are timed (the others can be forced)
   const int forced = forced_variant(int(key >> 56));
   if (forced >= 0 && forced < nvar) return forced;
+  if (ntime < 0) ntime = nvar;
   hifde_tree_s* tree = F.tree;
   if (tree) {
     auto it = tree->tune.find(key);
@@ -1148,7 +1175,7 @@ static int tune_choice(hifde_factor_s& F, uint64_t key, int nvar, int dflt, void
   F.events.push_back(b);
   float best = 0.f;
   int bi = dflt;
-  for (int v = 0; v < nvar; ++v) {
+  for (int v = 0; v < ntime; ++v) {
     // each variant twice, the faster run kept: a kernel's first launch in
     // the process also loads its code, which is no part of its cost
     float ms = 0.f;
@@ -1255,12 +1282,15 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   // the apply form's buffers (uploaded here, before the elimination is
   // queued: see apply_form)
   const InvWork<T> iw = apply_form_work<T>(F.mem, fs, st);
+  int* ldl_counter = F.mem.get<int>(1);
   const int var = tune_choice(
       F, tune_key(FAM_LDL, int(sizeof(T)), S.pmax, S.smax, S.ncell), LDL_VARIANTS, LDL_MFMA, D.pool,
       size_t(S.elems) * sizeof(T), st, [&](int v) {
-        batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, v);
-      });
-  batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, var);
+        batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, v,
+                       ldl_counter);
+      }, ldl_timed(S.ncell));
+  batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, var,
+                 ldl_counter);
   // The apply form and its packed copy are read by the sweeps only: they run
   // on the side stream after this level's IDs, beside the host's skeleton
   // bookkeeping and the next level's planning.  They touch the first p
@@ -1483,6 +1513,7 @@ static void skeleton_fronts(hifde_factor_s& F, GroupLevel& G, const Level& lev,
   {
     const std::vector<FrontDev> fs = sorted_by_p(G.ff);
     const FrontDev* fs_d = F.mem.upload(fs, st);
+    int* ldl_counter = F.mem.get<int>(1);
     int pmx = 0, smx = 0;
     for (const FrontDev& f : fs) {
       pmx = std::max(pmx, f.p);
@@ -1491,9 +1522,11 @@ static void skeleton_fronts(hifde_factor_s& F, GroupLevel& G, const Level& lev,
     const int var = tune_choice(
         F, tune_key(FAM_LDL, int(sizeof(T)), pmx, smx, G.nskel), LDL_VARIANTS, LDL_MFMA, G.fg,
         size_t(fg_off) * sizeof(T), st, [&](int v) {
-          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, v);
-        });
-    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, var);
+          batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, v,
+                         ldl_counter);
+        }, ldl_timed(G.nskel));
+    batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, var,
+                   ldl_counter);
     const int ivar = tune_choice(
         F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 2, 1, G.fg,
         size_t(fg_off) * sizeof(T), st,

@@ -1,7 +1,8 @@
 """GPU: the bucketed, persistent and autotuned launch paths.
 
 Every launch variant the autotuner can pick (trailing update of the batched
-LDL^T and the apply-form step on FMA or on the matrix cores; ID launch as
+LDL^T and the apply-form step on FMA or on the matrix cores, or the whole
+LDL^T of a level in one persistent launch; ID launch as
 one work-group per group, as a persistent queue, largest first, or in the
 wide form that spreads each step over many work-groups) must give the oracle's index sets
 and, in FP64, F^-1 f within the parity bar; autotuning records its choices
@@ -20,7 +21,8 @@ torch = pytest.importorskip("torch")
 
 @pytest.mark.parametrize("force", ["ldl=0,cpqr=0,inv=0", "ldl=1,cpqr=1,inv=1",
                                    "ldl=0,cpqr=1,inv=1", "ldl=1,cpqr=0,inv=0",
-                                   "ldl=1,cpqr=2,inv=1", "ldl=1,cpqr=3,inv=1"])
+                                   "ldl=1,cpqr=2,inv=1", "ldl=1,cpqr=3,inv=1",
+                                   "ldl=2,cpqr=0,inv=1"])
 @pytest.mark.parametrize("case", [(2, 64, 8, 1e-6, "bernoulli_contrast", 2),
                                   (3, 16, 2, 1e-3, "lognormal_grf", 4)])
 def test_every_variant_matches_oracle(force, case, monkeypatch):
@@ -57,3 +59,25 @@ def test_autotune_caches_choices_in_tree(prec):
     f = torch.from_numpy(W.make_rhs(n * n, 3, 2)).cuda()
     u1, u2 = H.hifde_solve(F1, f), H.hifde_solve(F2, f)
     assert torch.equal(u1, u2)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("case", [(2, 128, 8, "bernoulli_contrast", 2),
+                                  (3, 32, 4, "const", None)])
+def test_persistent_ldl_is_bitwise_the_panel_launches(prec, case, monkeypatch):
+    """The one-launch-per-level LDL^T runs every front's panels with the
+    tile arithmetic of the per-panel launches: the factors are bitwise
+    equal."""
+    import paper_1307_2895_amd as H
+    dim, n, m, field, seed = case
+    print(f"case persistent ldl {case} prec={prec}", flush=True)
+    a = W.make_field(dim, n, field, seed)
+    f = torch.from_numpy(W.make_rhs(n ** dim, 2, 4)).cuda()
+    out = []
+    for force in ("ldl=1", "ldl=2"):
+        monkeypatch.setenv("HIFDE_TUNE_FORCE", force)
+        T = H.hifde_build_tree(dim, n, m, 0)
+        F = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+        out.append(H.hifde_solve(F, f))
+        F.free()
+    assert torch.equal(out[0], out[1])
