@@ -972,6 +972,12 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
 // upper 3D levels) splits its finished columns into ranges of whole panels,
 // at most kInvSplitMax and at least four panels each.
 constexpr int kInvSplitMax = 16;
+// Apply-form variants: 0 column blocks on FMA, 1 column blocks on the
+// matrix cores, 2 recursive doubling (a single front with s = p only).
+constexpr int INV_DOUBLING = 2;
+static inline bool doubling_applies(const std::vector<FrontDev>& fh) {
+  return fh.size() == 1 && fh[0].s == fh[0].p && fh[0].p > kNB;
+}
 struct InvStep {
   int J = 0;
   unsigned na = 0;
@@ -1042,6 +1048,29 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
                        const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
                        bool sorted = false, int variant = 1, const InvWork<T>* work = nullptr) {
   if (fh.empty()) return;
+  if (variant == INV_DOUBLING && doubling_applies(fh) && !bounds) {
+    // a single front without trailing block: recursive doubling
+    const FrontDev& f = fh[0];
+    const int n = f.p;
+    T* S = pool + f.off;
+    const int64_t ld = f.s;
+    hipLaunchKernelGGL(k_inv_mirror<T>, dim3(unsigned((n + kNB - 1) / kNB)), dim3(kThreads), 0, st,
+                       S, ld, n);
+    int64_t tmax = 1;
+    for (int64_t bs = kNB; bs < n; bs *= 2)
+      tmax = std::max<int64_t>(tmax, ((n + 2 * bs - 1) / (2 * bs)) * bs * bs);
+    T* tmp = mem.get<T>(size_t(tmax));
+    for (int bs = kNB; bs < n; bs *= 2) {
+      const unsigned pairs = unsigned((n + 2 * int64_t(bs) - 1) / (2 * int64_t(bs)));
+      const unsigned t1 = unsigned((bs + kTB - 1) / kTB);
+      for (int mode = 0; mode < 2; ++mode)
+        hipLaunchKernelGGL(k_inv_double<T>, dim3(pairs, t1 * t1), dim3(kThreads), 0, st, S, ld, n,
+                           bs, tmp, mode);
+    }
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+  if (variant == INV_DOUBLING) variant = 1;
   const InvWork<T> w = work ? *work : apply_form_work<T>(mem, fh, st, bounds, sorted);
   T* tmp = w.tmp;
   const int64_t* toff_d = w.toff;
@@ -1297,9 +1326,13 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   // columns of each front; the groups and later levels read the update
   // blocks.
   F.side_work = [&F, &D, &S, fs = std::move(fs), fs_d, iw](hipStream_t ss) {
+    // the top block (one front, no trailing block) defaults to the doubling
+    // form from 256 pivots on
+    const bool dbl = doubling_applies(fs);
     const int ivar = tune_choice(
-        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 2, 1, D.pool,
-        size_t(S.elems) * sizeof(T), ss, [&](int v) {
+        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), dbl ? 3 : 2,
+        dbl && fs[0].p >= 256 ? INV_DOUBLING : 1, D.pool, size_t(S.elems) * sizeof(T), ss,
+        [&](int v) {
           apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v, &iw);
         });
     apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar, &iw);

@@ -2,7 +2,8 @@
 
 Every launch variant the autotuner can pick (trailing update of the batched
 LDL^T and the apply-form step on FMA or on the matrix cores, or the whole
-LDL^T of a level in one persistent launch; ID launch as
+LDL^T of a level in one persistent launch; the top block's apply form by
+column blocks or by recursive doubling; ID launch as
 one work-group per group, as a persistent queue, largest first, or in the
 wide form that spreads each step over many work-groups) must give the oracle's index sets
 and, in FP64, F^-1 f within the parity bar; autotuning records its choices
@@ -22,7 +23,7 @@ torch = pytest.importorskip("torch")
 @pytest.mark.parametrize("force", ["ldl=0,cpqr=0,inv=0", "ldl=1,cpqr=1,inv=1",
                                    "ldl=0,cpqr=1,inv=1", "ldl=1,cpqr=0,inv=0",
                                    "ldl=1,cpqr=2,inv=1", "ldl=1,cpqr=3,inv=1",
-                                   "ldl=2,cpqr=0,inv=1"])
+                                   "ldl=2,cpqr=0,inv=1", "ldl=1,cpqr=0,inv=2"])
 @pytest.mark.parametrize("case", [(2, 64, 8, 1e-6, "bernoulli_contrast", 2),
                                   (3, 16, 2, 1e-3, "lognormal_grf", 4)])
 def test_every_variant_matches_oracle(force, case, monkeypatch):
@@ -81,3 +82,27 @@ def test_persistent_ldl_is_bitwise_the_panel_launches(prec, case, monkeypatch):
         out.append(H.hifde_solve(F, f))
         F.free()
     assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("case", [(3, 32, 4, "const", None), (3, 16, 2, "lognormal_grf", 4),
+                                  (2, 256, 4, "bernoulli_contrast", 2)])
+def test_top_block_doubling_matches_column_blocks(case, monkeypatch):
+    """The top block's inverse by recursive doubling (products of inverted
+    blocks) and by column blocks agree to rounding: F^-1 f within 1e-12 in
+    FP64 (the top blocks here have 200 to 900 unknowns)."""
+    import paper_1307_2895_amd as H
+    dim, n, m, field, seed = case
+    print(f"case top doubling {case}", flush=True)
+    a = W.make_field(dim, n, field, seed)
+    f = torch.from_numpy(W.make_rhs(n ** dim, 2, 5)).cuda()
+    out = []
+    for force in ("inv=1", "inv=2"):
+        monkeypatch.setenv("HIFDE_TUNE_FORCE", force)
+        T = H.hifde_build_tree(dim, n, m, 0)
+        F = H.hifde_factor(T, torch_inputs(a), None, 1e-6, H.HIFDE_FP64)
+        print("top", H.hifde_stats(F)["top_size"])
+        out.append(H.hifde_solve(F, f).cpu().numpy())
+        F.free()
+    d = np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[0])
+    print("difference", d)
+    assert d <= 1e-12
