@@ -1363,15 +1363,6 @@ static void report_info(const std::vector<int>& h, const char* what, int l, bool
     }
 }
 
-static void check_info(const int* info, size_t n, const char* what, int l, bool definite,
-                       hipStream_t st) {
-  if (n == 0) return;
-  std::vector<int> h(n);
-  HIP_CHECK(hipMemcpyAsync(h.data(), info, n * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipStreamSynchronize(st));
-  report_info(h, what, l, definite);
-}
-
 // Pivot flags of the level-l cells and of the level l-1/2 skeleton fronts,
 // queued for the host beside the level's ranks: a block that is not positive
 // definite stops the factorization at the first synchronization after it
@@ -2025,13 +2016,42 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
   }
   if (F.plan_only) return;
   check_input(F, st);
-  // pivot checks of every level at once (one synchronization)
-  for (int l = 0; l <= L; ++l) {
-    check_info(F.cl[l].info, F.cl[l].st->fh.size(), l == L ? "top block" : "cell", l,
-               F.definite, st);
-    if (l < L && F.gl[l].info) {
-      const size_t ni = F.presize ? size_t(F.gl[l].ngroup) : size_t(F.gl[l].nskel);
-      if (ni > 0) check_info(F.gl[l].info, ni, "group", l, F.definite, st);
+  // pivot checks of every level at once: the flags are gathered on the
+  // device and read back in one copy (one synchronization)
+  {
+    struct Part {
+      const int* info;
+      size_t n;
+      const char* what;
+      int l;
+    };
+    std::vector<Part> parts;
+    size_t total = 0;
+    for (int l = 0; l <= L; ++l) {
+      const size_t nc = F.cl[l].st->fh.size();
+      if (F.cl[l].info && nc > 0) parts.push_back({F.cl[l].info, nc, l == L ? "top block" : "cell", l});
+      if (l < L && F.gl[l].info) {
+        const size_t ni = F.presize ? size_t(F.gl[l].ngroup) : size_t(F.gl[l].nskel);
+        if (ni > 0) parts.push_back({F.gl[l].info, ni, "group", l});
+      }
+    }
+    for (const Part& q : parts) total += q.n;
+    if (total > 0) {
+      int* all = F.mem.get<int>(total);
+      size_t at = 0;
+      for (const Part& q : parts) {
+        HIP_CHECK(hipMemcpyAsync(all + at, q.info, q.n * sizeof(int), hipMemcpyDeviceToDevice, st));
+        at += q.n;
+      }
+      std::vector<int> h(total);
+      HIP_CHECK(hipMemcpyAsync(h.data(), all, total * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      at = 0;
+      for (const Part& q : parts) {
+        report_info(std::vector<int>(h.begin() + at, h.begin() + at + q.n), q.what, q.l,
+                    F.definite);
+        at += q.n;
+      }
     }
   }
   tm.mark("pivot checks", L);
