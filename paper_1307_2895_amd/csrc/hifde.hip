@@ -973,10 +973,10 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
 // at most kInvSplitMax and at least four panels each.
 constexpr int kInvSplitMax = 16;
 // Apply-form variants: 0 column blocks on FMA, 1 column blocks on the
-// matrix cores, 2 recursive doubling (a single front with s = p only).
+// matrix cores, 2 recursive doubling.
 constexpr int INV_DOUBLING = 2;
-static inline bool doubling_applies(const std::vector<FrontDev>& fh) {
-  return fh.size() == 1 && fh[0].s == fh[0].p && fh[0].p > kNB;
+static inline bool single_top(const std::vector<FrontDev>& fh) {
+  return fh.size() == 1 && fh[0].s == fh[0].p;
 }
 struct InvStep {
   int J = 0;
@@ -1048,24 +1048,42 @@ static void apply_form(Arena& mem, T* pool, const std::vector<FrontDev>& fh,
                        const FrontDev* fronts_d, hipStream_t st, bool bounds = false,
                        bool sorted = false, int variant = 1, const InvWork<T>* work = nullptr) {
   if (fh.empty()) return;
-  if (variant == INV_DOUBLING && doubling_applies(fh) && !bounds) {
-    // a single front without trailing block: recursive doubling
-    const FrontDev& f = fh[0];
-    const int n = f.p;
-    T* S = pool + f.off;
-    const int64_t ld = f.s;
-    hipLaunchKernelGGL(k_inv_mirror<T>, dim3(unsigned((n + kNB - 1) / kNB)), dim3(kThreads), 0, st,
-                       S, ld, n);
-    int64_t tmax = 1;
-    for (int64_t bs = kNB; bs < n; bs *= 2)
-      tmax = std::max<int64_t>(tmax, ((n + 2 * bs - 1) / (2 * bs)) * bs * bs);
-    T* tmp = mem.get<T>(size_t(tmax));
-    for (int bs = kNB; bs < n; bs *= 2) {
-      const unsigned pairs = unsigned((n + 2 * int64_t(bs) - 1) / (2 * int64_t(bs)));
-      const unsigned t1 = unsigned((bs + kTB - 1) / kTB);
+  if (variant == INV_DOUBLING && !bounds) {
+    // recursive doubling for every front (exact pivot counts only)
+    int pmax = 0;
+    int64_t qpmax = 0;
+    for (const FrontDev& f : fh) {
+      pmax = std::max(pmax, f.p);
+      qpmax = std::max<int64_t>(qpmax, int64_t(f.s - f.p) * f.p);
+    }
+    const unsigned nf = unsigned(fh.size());
+    if (pmax == 0) return;
+    hipLaunchKernelGGL(k_inv_mirror<T>, dim3(nf, unsigned((pmax + kNB - 1) / kNB)), dim3(kThreads),
+                       0, st, pool, fronts_d);
+    int64_t smax_tmp = 0;
+    for (int64_t bs = kNB; bs < pmax; bs *= 2)
+      smax_tmp = std::max<int64_t>(smax_tmp, ((pmax + 2 * bs - 1) / (2 * bs)) * bs * bs);
+    if (smax_tmp > 0) {
+      T* tmp = mem.get<T>(size_t(smax_tmp) * nf);
+      for (int bs = kNB; bs < pmax; bs *= 2) {
+        const int64_t pairs = (pmax + 2 * int64_t(bs) - 1) / (2 * int64_t(bs));
+        const int64_t t1 = (bs + kTB - 1) / kTB;
+        const int64_t stride = pairs * bs * bs;
+        if (pairs * t1 * t1 > 65535) throw Error(HIFDE_EINVAL, "front too large for the doubling grid");
+        for (int mode = 0; mode < 2; ++mode)
+          hipLaunchKernelGGL(k_inv_double<T>, dim3(nf, unsigned(pairs * t1 * t1)), dim3(kThreads), 0,
+                             st, pool, fronts_d, bs, tmp, stride, mode);
+      }
+    }
+    if (qpmax > 0) {
+      int qmax = 0;
+      for (const FrontDev& f : fh) qmax = std::max(qmax, f.s - f.p);
+      const int64_t tiles = int64_t((qmax + kTB - 1) / kTB) * ((pmax + kTB - 1) / kTB);
+      if (tiles > 65535) throw Error(HIFDE_EINVAL, "front too large for the doubling grid");
+      T* tq = mem.get<T>(size_t(qpmax) * nf);
       for (int mode = 0; mode < 2; ++mode)
-        hipLaunchKernelGGL(k_inv_double<T>, dim3(pairs, t1 * t1), dim3(kThreads), 0, st, S, ld, n,
-                           bs, tmp, mode);
+        hipLaunchKernelGGL(k_inv_rows<T>, dim3(nf, unsigned(tiles)), dim3(kThreads), 0, st, pool,
+                           fronts_d, tq, qpmax, mode);
     }
     HIP_CHECK(hipGetLastError());
     return;
@@ -1328,11 +1346,10 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   F.side_work = [&F, &D, &S, fs = std::move(fs), fs_d, iw](hipStream_t ss) {
     // the top block (one front, no trailing block) defaults to the doubling
     // form from 256 pivots on
-    const bool dbl = doubling_applies(fs);
     const int ivar = tune_choice(
-        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), dbl ? 3 : 2,
-        dbl && fs[0].p >= 256 ? INV_DOUBLING : 1, D.pool, size_t(S.elems) * sizeof(T), ss,
-        [&](int v) {
+        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 3,
+        single_top(fs) && fs[0].p >= 256 ? INV_DOUBLING : 1, D.pool,
+        size_t(S.elems) * sizeof(T), ss, [&](int v) {
           apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v, &iw);
         });
     apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, ivar, &iw);
@@ -1552,7 +1569,7 @@ static void skeleton_fronts(hifde_factor_s& F, GroupLevel& G, const Level& lev,
     batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, var,
                    ldl_counter);
     const int ivar = tune_choice(
-        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 2, 1, G.fg,
+        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 3, 1, G.fg,
         size_t(fg_off) * sizeof(T), st,
         [&](int v) { apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, v); });
     apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, ivar);

@@ -85,11 +85,14 @@ def test_persistent_ldl_is_bitwise_the_panel_launches(prec, case, monkeypatch):
 
 
 @pytest.mark.parametrize("case", [(3, 32, 4, "const", None), (3, 16, 2, "lognormal_grf", 4),
-                                  (2, 256, 4, "bernoulli_contrast", 2)])
-def test_top_block_doubling_matches_column_blocks(case, monkeypatch):
-    """The top block's inverse by recursive doubling (products of inverted
-    blocks) and by column blocks agree to rounding: F^-1 f within 1e-12 in
-    FP64 (the top blocks here have 200 to 900 unknowns)."""
+                                  (2, 256, 4, "bernoulli_contrast", 2),
+                                  (2, 256, 16, "bernoulli_contrast", 2),
+                                  (2, 250, 16, "loguniform", 3)])
+def test_doubling_apply_form_matches_column_blocks(case, monkeypatch):
+    """The apply forms by recursive doubling (inverted halves joined by
+    products, then the rows below the pivots) and by column blocks agree to
+    rounding on every level: F^-1 f within 1e-12 in FP64 (fronts of 47 to
+    1600 pivots, ragged and power-of-two sizes)."""
     import paper_1307_2895_amd as H
     dim, n, m, field, seed = case
     print(f"case top doubling {case}", flush=True)
