@@ -41,7 +41,7 @@ DOMINANT_SOURCE = os.path.join(ROOT, "paper_1307_2895_amd", "csrc", "kernels_sol
 CALIB_COPY_BYTES = 512 << 20
 # workloads timed beside the headline one (3D configurations; the last with
 # 256 and with 1 right-hand side on the same factorization)
-EXTRA_WORKLOADS = ("laplace3d_n64", "grf3d_n128", "helmholtz2d_n1024")
+EXTRA_WORKLOADS = ("laplace3d_n64", "grf3d_n128", "helmholtz2d_n1024", "helmholtz3d_n64")
 
 
 def dominant_kernel(mixed, nrhs):

@@ -600,7 +600,7 @@ struct hifde_factor_s {
   }
   void use_pool(std::shared_ptr<MemPool> p) {
     pool = std::move(p);
-    for (DevMem* m : {&diag, &offd, &X, &Z, &pcg}) m->pool = pool.get();
+    for (DevMem* m : {&diag, &offd, &X, &Z, &C, &pcg, &gm}) m->pool = pool.get();
     mem.pool = pool.get();
   }
   // Releases the runtime handles (idempotent).
@@ -978,6 +978,8 @@ constexpr int INV_DOUBLING = 2;
 static inline bool single_top(const std::vector<FrontDev>& fh) {
   return fh.size() == 1 && fh[0].s == fh[0].p;
 }
+// Apply-form variants open to the tuner (and to forcing) by type.
+template <typename T> static inline int inv_variants() { return sizeof(T) == 8 ? 3 : 2; }
 struct InvStep {
   int J = 0;
   unsigned na = 0;
@@ -1345,9 +1347,11 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
   // blocks.
   F.side_work = [&F, &D, &S, fs = std::move(fs), fs_d, iw](hipStream_t ss) {
     // the top block (one front, no trailing block) defaults to the doubling
-    // form from 256 pivots on
+    // form from 256 pivots on; float fronts keep the column blocks (the
+    // doubling's products of inverted blocks round less favourably there,
+    // which shows on indefinite fronts)
     const int ivar = tune_choice(
-        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), 3,
+        F, tune_key(FAM_INV, int(sizeof(T)), S.pmax, S.smax, S.ncell), inv_variants<T>(),
         single_top(fs) && fs[0].p >= 256 ? INV_DOUBLING : 1, D.pool,
         size_t(S.elems) * sizeof(T), ss, [&](int v) {
           apply_form<T>(F.mem, static_cast<T*>(D.pool), fs, fs_d, ss, false, true, v, &iw);
@@ -1569,7 +1573,7 @@ static void skeleton_fronts(hifde_factor_s& F, GroupLevel& G, const Level& lev,
     batched_ldl<T>(static_cast<T*>(G.fg), fs, fs_d, G.info, F.definite, st, false, true, var,
                    ldl_counter);
     const int ivar = tune_choice(
-        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), 3, 1, G.fg,
+        F, tune_key(FAM_INV, int(sizeof(T)), pmx, smx, G.nskel), inv_variants<T>(), 1, G.fg,
         size_t(fg_off) * sizeof(T), st,
         [&](int v) { apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, v); });
     apply_form<T>(F.mem, static_cast<T*>(G.fg), fs, fs_d, st, false, true, ivar);

@@ -77,6 +77,12 @@ WORKLOADS: Dict[str, Workload] = {
         "helmholtz2d_n1024", 2, 1024, 16, 1e-6, "const", 16, None, 50, "mixed_elim64",
         "2D Helmholtz, 32 wavelengths across the square, N=1048576, leaf 16x16",
         wavelengths=32.0),
+    # Example 6: the 3D analogue at 8 unknowns per wavelength (kappa = 8 on
+    # the 64^3 grid)
+    "helmholtz3d_n64": Workload(
+        "helmholtz3d_n64", 3, 64, 4, 1e-6, "const", 16, None, 60, "mixed_elim64",
+        "3D Helmholtz, 8 wavelengths across the cube, N=262144, leaf 4^3",
+        wavelengths=8.0, sketch=True),
 }
 
 

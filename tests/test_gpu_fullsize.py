@@ -111,25 +111,35 @@ def test_full_size(name, nrhs):
     assert x[:, 0] @ z[:, 0] > 0 and x[:, 1] @ z[:, 1] > 0
 
 
-def test_full_size_helmholtz():
-    """Example 3's indefinite Helmholtz problem at 32 unknowns per
-    wavelength (about 3200 negative eigenvalues of A, from the closed form):
-    GMRES preconditioned by the indefinite factor reaches 1e-12 in a few
-    steps; the reported true residual equals the one recomputed from the
-    oracle's assembled A; F^-1 is symmetric to the sweeps' precision."""
+@pytest.mark.parametrize("name,neg_range,max_rel,max_its", [
+    ("helmholtz2d_n1024", (3000, 3400), 1e-11, 12),
+    # 8 unknowns per wavelength, float factor with the randomized ID: about
+    # 12 steps; condition number about 3.4e4, so the attainable residual is
+    # allowed to be larger than in 2D
+    ("helmholtz3d_n64", (1900, 2000), 1e-10, 30),
+])
+def test_full_size_helmholtz(name, neg_range, max_rel, max_its):
+    """Examples 3 and 6: the indefinite Helmholtz problems (about 3200 and
+    1950 negative eigenvalues of A, from the closed form): GMRES
+    preconditioned by the indefinite factor converges in a few steps; the
+    reported true residual equals the one recomputed from the oracle's
+    assembled A; F^-1 is symmetric to the sweeps' precision."""
     import paper_1307_2895_amd as H
-    w = W.workload("helmholtz2d_n1024")
+    w = W.workload(name)
     print(f"case {w.name}", flush=True)
     a = W.make_coefficients(w)
     b = W.make_b(w)
     h = 1.0 / (w.n + 1)
     lam = 4 / h ** 2 * np.sin(np.arange(1, w.n + 1) * np.pi * h / 2) ** 2
-    neg = int(np.sum(lam[:, None] + lam[None, :] + b[0] < 0))
-    assert 3000 < neg < 3400, neg
+    tot = lam
+    for _ in range(w.dim - 1):
+        tot = np.add.outer(tot, lam)
+    neg = int(np.sum(tot + b[0] < 0))
+    assert neg_range[0] < neg < neg_range[1], neg
     T = H.hifde_build_tree(w.dim, w.n, w.leaf, 0)
     prec = H.PRECISIONS[w.precision]
     F = H.hifde_factor(T, torch_inputs(a), torch.from_numpy(b).cuda(), w.eps, prec,
-                       flags=H.HIFDE_INDEFINITE)
+                       flags=H.HIFDE_INDEFINITE | (H.HIFDE_SKETCH_ID if w.sketch else 0))
     _check_tree(F, w)
     f = W.make_rhs(w.N, w.nrhs, w.seed_f)
     u, its, rel = H.hifde_gmres(F, torch.from_numpy(f).cuda(), tol=1e-12, restart=30, maxit=200)
@@ -137,9 +147,9 @@ def test_full_size_helmholtz():
     A = OP.assemble(w.dim, w.n, a, b).tocsr()
     true = _residual_ext(A, u, f)
     print(w.name, "iterations", its, "true residual", true.max(), "reported", np.max(rel))
-    assert np.all(true <= 1e-11), true
+    assert np.all(true <= max_rel), true
     assert np.all(np.abs(true - rel) <= 0.1 * true + 1e-12), (true, rel)
-    assert np.all(its <= 12), its
+    assert np.all(its <= max_its), its
     rng = np.random.default_rng(2)
     x = rng.standard_normal((w.N, 2))
     z = H.hifde_solve(F, torch.from_numpy(x).cuda()).cpu().numpy()

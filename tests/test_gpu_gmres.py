@@ -214,3 +214,35 @@ def test_indefinite_levels_fail_without_the_flag():
     assert ei.value.code == H.HIFDE_ENOTSPD
     _, F = _factor(n, m, a, b, 1e-6, H.HIFDE_MIXED_ELIM64)
     F.free()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("eps,sketch", [(1e-6, False), (1e-3, False), (1e-6, True), (1e-3, True)])
+def test_gmres_3d_matches_oracle(eps, sketch, prec):
+    """The 3D analogue (Example 6) on the 16^3 grid at 8 unknowns per
+    wavelength (kappa = 2: 17 negative eigenvalues, |lambda| >= 6.7 from the
+    closed form), with and without the randomized ID on both sides."""
+    import paper_1307_2895_amd as H
+    n, m = 16, 4
+    b = W.helmholtz_b(n ** 3, 2.0)
+    a = W.make_field(3, n, "const", None)
+    A = problem.assemble(3, n, a, b)
+    f = W.make_rhs(n ** 3, 2, 7)
+    OF = OH.factor(3, n, m, a, b=b, eps=eps, definite=False, sketch=sketch)
+    _, oits, _ = OG.gmres_multi(A, f, lambda r: OH.solve(OF, r), 1e-12, 30, 100)
+    ud = spla.spsolve(A.tocsc(), f)
+    print(f"case 3d eps={eps} sketch={sketch} prec={prec}", flush=True)
+    T = H.hifde_build_tree(3, n, m, 0)
+    flags = H.HIFDE_INDEFINITE | (H.HIFDE_SKETCH_ID if sketch else 0)
+    F = H.hifde_factor(T, torch_inputs(a), torch.from_numpy(b).cuda(), eps, prec, flags=flags)
+    u, its, rel = H.hifde_gmres(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=100)
+    u = u.cpu().numpy()
+    err = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+    print("oracle iters", oits, "gpu iters", its, "relres", rel, "err", err)
+    assert np.all(rel <= 1e-12)
+    if prec == 0:
+        assert np.all(np.abs(its - oits) <= 1), (its, oits)
+    else:
+        assert np.all(its <= 2 * oits + 2), (its, oits)
+    assert err <= 1e-9
+    F.free()
