@@ -246,3 +246,22 @@ def test_gmres_3d_matches_oracle(eps, sketch, prec):
         assert np.all(its <= 2 * oits + 2), (its, oits)
     assert err <= 1e-9
     F.free()
+
+
+def test_gmres_many_columns():
+    """300 right-hand sides (more than a work-group's threads: the inner
+    products take the columns 256 at a time) on a small indefinite grid:
+    every column converges to the sparse direct solution."""
+    import paper_1307_2895_amd as H
+    n, m, bneg = 32, 8, -60.0
+    a, b, A = _problem(n, bneg)
+    f = W.make_rhs(n * n, 300, 14)
+    T, F = _factor(n, m, a, b, 1e-6, H.HIFDE_FP64)
+    u, its, rel = H.hifde_gmres(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=50)
+    u = u.cpu().numpy()
+    ud = spla.spsolve(A.tocsc(), f)
+    print("iterations", its.min(), its.max(), "relres", rel.max())
+    assert np.all(rel <= 1e-12)
+    err = np.linalg.norm(u - ud, axis=0) / np.linalg.norm(ud, axis=0)
+    assert np.all(err <= 1e-9), err.max()
+    F.free()
