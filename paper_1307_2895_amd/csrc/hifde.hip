@@ -848,7 +848,8 @@ static void upload_group_static(GroupStatic& gs, Arena& mem, hipStream_t st) {
 
 // Grid of a front_tile launch: nf fronts, nt tiles each.
 static unsigned front_tile_grid(unsigned nf, int64_t nt, const char* what) {
-  const int64_t g = int64_t(8) * ((nf + 7) / 8) * nt;
+  const int64_t per = nf >= 8 ? 0 : 8 / front_tile_round(int(nf));
+  const int64_t g = nf >= 8 ? int64_t(8) * ((nf + 7) / 8) * nt : int64_t(8) * ((nt + per - 1) / per);
   if (g > INT32_MAX) throw Error(HIFDE_EINVAL, std::string("front too large for the ") + what);
   return unsigned(g);
 }
