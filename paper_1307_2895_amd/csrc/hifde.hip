@@ -1311,10 +1311,13 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
         tmax = std::max<int64_t>(tmax, f.trip_end - f.trip_begin);
       }
       for (const SrcDev& d : S.srcs_h) dmax = std::max(dmax, d.dim);
+      const AsmChunks ch = asm_chunks(S.ncell, dmax);
       for (int r = 0; r < rounds; ++r)
-        hipLaunchKernelGGL((k_assemble_round<T>), dim3(S.ncell, (dmax + kAsmCols - 1) / kAsmCols),
+        hipLaunchKernelGGL((k_assemble_round<T>),
+                           dim3(S.ncell, (dmax + ch.cols - 1) / ch.cols,
+                                (dmax + ch.rows - 1) / ch.rows),
                            dim3(kThreads), 0, st, static_cast<T*>(D.pool), S.fronts, S.srcs, S.maps,
-                           r, pt);
+                           r, pt, ch.cols, ch.rows);
       if (tmax > 0)
         hipLaunchKernelGGL(k_assemble_trips<T>, dim3(S.ncell, unsigned((tmax + 4095) / 4096)),
                            dim3(kThreads), 0, st, static_cast<T*>(D.pool), S.fronts, S.trips,
@@ -1653,10 +1656,12 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
     }
     for (const SrcDev& d : S.gsrcs_h) dmax = std::max(dmax, d.dim);
     const unsigned ng = unsigned(G.ngroup);
+    const AsmChunks ch = asm_chunks(ng, dmax);
     for (int r = 0; r < rounds; ++r)
-      hipLaunchKernelGGL(k_gather_round<T>, dim3(ng, (dmax + kAsmCols - 1) / kAsmCols),
+      hipLaunchKernelGGL(k_gather_round<T>,
+                         dim3(ng, (dmax + ch.cols - 1) / ch.cols, (dmax + ch.rows - 1) / ch.rows),
                          dim3(kThreads), 0, st, static_cast<T*>(G.gw), G.groups, S.gsrcs, S.maps, r,
-                         pt_cur);
+                         pt_cur, ch.cols, ch.rows);
     hipLaunchKernelGGL(k_gather_base<T>, dim3(ng, (ncmax + kAsmCols - 1) / kAsmCols),
                        dim3(kThreads), 0, st, static_cast<T*>(G.gw),
                        static_cast<const T*>(G.base), G.groups);
