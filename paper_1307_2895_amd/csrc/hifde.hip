@@ -1780,6 +1780,10 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(upd_lds)));
       hipLaunchKernelGGL(k_cpqr_w_init<T>, dim3(ng, chunks), dim3(kThreads), 0, st,
                          idw, idg, list_d, norms, noff_d, permw, stw);
+      // the host waits inside the step loop (the rank checks below): the
+      // side stream's work is released now so that it runs beside the steps
+      // (few work-groups each) instead of after them
+      F.flush_side(st);
       for (int j = 0; j < maxsteps; ++j) {
         hipLaunchKernelGGL(k_cpqr_w_pivot<T>, dim3(ng), dim3(kThreads), 0, st,
                            idw, idg, list_d, norms, noff_d, permw, stw, j,
