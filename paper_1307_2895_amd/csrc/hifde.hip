@@ -176,6 +176,33 @@ struct StreamCache {
   }
 };
 
+// Pinned host buffers for the small read-backs of factorizations and
+// solves (ranks, pivots, flags, Hessenberg columns).  A copy into pageable
+// memory goes through the runtime's staging path, which has been seen to
+// start only after work queued earlier on another stream (the side
+// stream's apply forms); a copy into pinned memory keeps just its own
+// stream's order.  Kept for the life of the process, like the streams.
+struct PinnedCache {
+  std::mutex mu;
+  std::vector<std::pair<void*, size_t>> kept;
+  static PinnedCache& get() {
+    static PinnedCache* c = new PinnedCache;       // never destroyed
+    return *c;
+  }
+  std::pair<void*, size_t> take() {
+    std::lock_guard<std::mutex> g(mu);
+    if (kept.empty()) return {nullptr, 0};
+    auto b = kept.back();
+    kept.pop_back();
+    return b;
+  }
+  void give(void* p, size_t cap) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu);
+    kept.emplace_back(p, cap);
+  }
+};
+
 inline void DevMem::release() {
   if (p) {
     if (pool) pool->give(p, cap);
@@ -558,6 +585,27 @@ struct hifde_factor_s {
   bool use_graph = true;
   bool row_tiles = false;                  // HIFDE_SWEEP_ROW_TILES
   int* bad_d = nullptr;                    // k_stencil's input flags
+  // Pinned buffer of at least n bytes for a read-back.  Every read-back
+  // synchronizes its stream before the next one asks, so the buffer is
+  // never replaced under a copy in flight.
+  void* hs = nullptr;
+  size_t hs_cap = 0;
+  void* host_stage(size_t n) {
+    if (!hs) {
+      auto b = PinnedCache::get().take();
+      hs = b.first;
+      hs_cap = b.second;
+    }
+    if (n > hs_cap) {
+      if (hs) HIP_CHECK(hipHostFree(hs));
+      hs = nullptr;
+      hs_cap = 0;
+      const size_t c = std::max<size_t>(n, size_t(1) << 20);
+      HIP_CHECK(hipHostMalloc(&hs, c, hipHostMallocDefault));
+      hs_cap = c;
+    }
+    return hs;
+  }
   bool input_checked = false;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -623,6 +671,9 @@ struct hifde_factor_s {
     gexec = nullptr;
     StreamCache::get().give(cap);
     cap = nullptr;
+    PinnedCache::get().give(hs, hs_cap);
+    hs = nullptr;
+    hs_cap = 0;
     for (ProfEvent& e : prof_ev) {
       if (e.a) (void)hipEventDestroy(e.a);
       if (e.b) (void)hipEventDestroy(e.b);
@@ -1369,9 +1420,10 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
 // The input flags of k_stencil (read once, at the first synchronization).
 static void check_input(hifde_factor_s& F, hipStream_t st) {
   if (F.input_checked || !F.bad_d) return;
-  int h = 0;
-  HIP_CHECK(hipMemcpyAsync(&h, F.bad_d, sizeof(int), hipMemcpyDeviceToHost, st));
+  int* hp = static_cast<int*>(F.host_stage(sizeof(int)));
+  HIP_CHECK(hipMemcpyAsync(hp, F.bad_d, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  const int h = *hp;
   F.input_checked = true;
   if (h & 1)
     throw Error(HIFDE_EINVAL, "a must be finite, positive on interior links, >= 0 on boundary links");
@@ -1394,21 +1446,37 @@ static void report_info(const std::vector<int>& h, const char* what, int l, bool
 // rather than after every later level.
 struct LevelPivots {
   std::vector<int> cells, groups;
-  void queue(const hifde_factor_s& F, int l, hipStream_t st) {
+  const int* cinfo = nullptr;
+  const int* ginfo = nullptr;
+  // the flag counts of level l (sizes the vectors); ints to stage
+  size_t count(const hifde_factor_s& F, int l) {
     const CellLevel& C = F.cl[l];
+    cinfo = ginfo = nullptr;
+    cells.clear();
+    groups.clear();
     if (C.info && C.st) {
       cells.resize(C.st->fh.size());
-      if (!cells.empty())
-        HIP_CHECK(hipMemcpyAsync(cells.data(), C.info, cells.size() * sizeof(int),
-                                 hipMemcpyDeviceToHost, st));
+      cinfo = C.info;
     }
     if (l > 0 && F.gl[l - 1].info) {
       const GroupLevel& G = F.gl[l - 1];
       groups.resize(F.presize ? size_t(G.ngroup) : size_t(G.nskel));
-      if (!groups.empty())
-        HIP_CHECK(hipMemcpyAsync(groups.data(), G.info, groups.size() * sizeof(int),
-                                 hipMemcpyDeviceToHost, st));
+      ginfo = G.info;
     }
+    return cells.size() + groups.size();
+  }
+  // copies into the pinned `stage` (count() ints)
+  void queue(int* stage, hipStream_t st) const {
+    if (!cells.empty())
+      HIP_CHECK(hipMemcpyAsync(stage, cinfo, cells.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (!groups.empty())
+      HIP_CHECK(hipMemcpyAsync(stage + cells.size(), ginfo, groups.size() * sizeof(int),
+                               hipMemcpyDeviceToHost, st));
+  }
+  // after the stream has synchronized
+  void collect(const int* stage) {
+    std::copy(stage, stage + cells.size(), cells.begin());
+    std::copy(stage + cells.size(), stage + cells.size() + groups.size(), groups.begin());
   }
   void check(int l, bool definite) const {   // after the stream has synchronized
     report_info(cells, "cell", l, definite);
@@ -1792,12 +1860,12 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
         hipLaunchKernelGGL(k_cpqr_w_update<T>, dim3(ng, uch), dim3(kThreads), upd_lds, st,
                            idw, idg, list_d, norms, noff_d, stw, j);
         if ((j & 31) == 31) {   // stop once every group has its rank
-          int live = 0;
+          int* live = static_cast<int*>(F.host_stage(sizeof(int)));
           hipLaunchKernelGGL(k_cpqr_w_live<T>, dim3(1), dim3(kThreads), 0, st, stw, G.ngroup,
                              live_d);
-          HIP_CHECK(hipMemcpyAsync(&live, live_d, sizeof(int), hipMemcpyDeviceToHost, st));
+          HIP_CHECK(hipMemcpyAsync(live, live_d, sizeof(int), hipMemcpyDeviceToHost, st));
           HIP_CHECK(hipStreamSynchronize(st));
-          if (live == 0) break;
+          if (*live == 0) break;
         }
       }
       hipLaunchKernelGGL(k_cpqr_w_tsolve<T>, dim3(ng, unsigned((ncmax + 63) / 64)), dim3(kThreads),
@@ -1885,12 +1953,17 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
   F.flush_side(st);   // after the IDs
   tm.mark("  side work", l);
   std::vector<int32_t> kh(G.ngroup), ph(size_t(G.ngroup) * ncmax);
-  // (copies to pageable memory return once the IDs are done)
-  HIP_CHECK(hipMemcpyAsync(kh.data(), G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(ph.data(), G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
   LevelPivots piv;
-  piv.queue(F, l, st);
+  const size_t npiv = piv.count(F, l);
+  int32_t* hk = static_cast<int32_t*>(F.host_stage((kh.size() + ph.size() + npiv) * 4));
+  int32_t* hp = hk + kh.size();
+  HIP_CHECK(hipMemcpyAsync(hk, G.kout, kh.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hp, G.perm, ph.size() * 4, hipMemcpyDeviceToHost, st));
+  piv.queue(hp + ph.size(), st);
   HIP_CHECK(hipStreamSynchronize(st));
+  std::copy(hk, hk + kh.size(), kh.begin());
+  std::copy(hp, hp + ph.size(), ph.begin());
+  piv.collect(hp + ph.size());
   tm.mark("  wait for IDs", l);
   check_input(F, st);
   piv.check(l, F.definite);
@@ -2074,9 +2147,10 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
         HIP_CHECK(hipMemcpyAsync(all + at, q.info, q.n * sizeof(int), hipMemcpyDeviceToDevice, st));
         at += q.n;
       }
-      std::vector<int> h(total);
-      HIP_CHECK(hipMemcpyAsync(h.data(), all, total * sizeof(int), hipMemcpyDeviceToHost, st));
+      int* hp = static_cast<int*>(F.host_stage(total * sizeof(int)));
+      HIP_CHECK(hipMemcpyAsync(hp, all, total * sizeof(int), hipMemcpyDeviceToHost, st));
       HIP_CHECK(hipStreamSynchronize(st));
+      const std::vector<int> h(hp, hp + total);
       at = 0;
       for (const Part& q : parts) {
         report_info(std::vector<int>(h.begin() + at, h.begin() + at + q.n), q.what, q.l,
@@ -2631,8 +2705,10 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_st), nr, 0, px, d1);
   std::vector<int> liveh(nr, 1), itsh(nr, 0);
   std::vector<double> fh(nr), h1(nr);
-  HIP_CHECK(hipMemcpyAsync(fh.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
+  double* hd = static_cast<double*>(F.host_stage(size_t(nr) * 8));   // pinned read-backs
+  HIP_CHECK(hipMemcpyAsync(hd, d1, nr * 8, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  std::copy(hd, hd + nr, fh.begin());
   for (int c = 0; c < nr; ++c) {
     fh[c] = std::sqrt(fh[c]);
     if (fh[c] == 0.0) liveh[c] = 0;
@@ -2657,8 +2733,9 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
                        diag, offd, alpha, pb, x, r, rc, flexible, px);
     hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_xr), nr, 0, px, d1);
     std::swap(pa, pb);
-    HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(hd, d1, nr * 8, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    std::copy(hd, hd + nr, h1.begin());
     bool changed = false, anyl = false;
     for (int c = 0; c < nr; ++c) {
       if (!liveh[c]) continue;
@@ -2682,9 +2759,10 @@ static bool run_pcg_w(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
   hipLaunchKernelGGL((k_pcg_true_resid<W, DIM>), dim3(nb_tr), dim3(kThreads), 0, st, N, nr, dn,
                      diag, offd, x, f, ldf, u, ldu, px);
   hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb_tr), nr, 0, px, d1);
-  HIP_CHECK(hipMemcpyAsync(h1.data(), d1, nr * 8, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hd, d1, nr * 8, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
+  std::copy(hd, hd + nr, h1.begin());
   bool converged = true;
   for (int c = 0; c < nr; ++c) {
     iters[c] = itsh[c];
@@ -2745,9 +2823,11 @@ static bool run_gmres(hifde_factor_s& F, int64_t nrhs, const double* f, int64_t 
     hipLaunchKernelGGL(k_gm_mgs, dim3(nb), dim3(kThreads), 0, st, N, nr, coef, vprev, v, w, part);
     hipLaunchKernelGGL(k_reduce_sum, dim3(nr), dim3(kThreads), 0, st, int(nb), nr, 0, part, out);
   };
+  double* hd = static_cast<double*>(F.host_stage(size_t(m + 2) * nr * 8));   // pinned
   auto read_h = [&](std::vector<double>& hh, int rows) {
-    HIP_CHECK(hipMemcpyAsync(hh.data(), h, size_t(rows) * nr * 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(hd, h, size_t(rows) * nr * 8, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    std::copy(hd, hd + size_t(rows) * nr, hh.begin());
   };
   const size_t ldh = size_t(m) + 1;              // H of column c: Hs[c][i + j ldh]
   std::vector<double> hh(size_t(m + 2) * nr), nf(nr, 0.0), denh(nr), Yh(size_t(m) * nr);
