@@ -1868,8 +1868,18 @@ static void groups_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream
           if (*live == 0) break;
         }
       }
-      hipLaunchKernelGGL(k_cpqr_w_tsolve<T>, dim3(ng, unsigned((ncmax + 63) / 64)), dim3(kThreads),
-                         0, st, idw, idg, list_d, stw);
+      // columns per work-group of the triangular solve: as many as the LDS
+      // holds for the largest possible rank
+      const int kmax = std::max(1, std::min(nnmax, ncmax));
+      int cw = 64;
+      while (cw > 1 && size_t(cw + 3) * kmax * sizeof(T) > 64 * 1024) cw /= 2;
+      const size_t ts_lds = size_t(cw + 3) * kmax * sizeof(T);
+      if (ts_lds > 160 * 1024) throw Error(HIFDE_EINVAL, "group too large for the ID's solve");
+      if (ts_lds > 64 * 1024)
+        HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cpqr_w_tsolve<T>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(ts_lds)));
+      hipLaunchKernelGGL(k_cpqr_w_tsolve<T>, dim3(ng, unsigned((ncmax + cw - 1) / cw)),
+                         dim3(kThreads), ts_lds, st, idw, idg, list_d, stw, cw);
       hipLaunchKernelGGL(k_cpqr_w_finish<T>, dim3(ng), dim3(kThreads), size_t(ncmax) * sizeof(int),
                          st, idw, static_cast<T*>(G.tpool), idg, list_d,
                          noff_d, permw, stw, G.kout, G.perm, G.perm_stride);
