@@ -444,6 +444,12 @@ struct CellStatic {
   std::vector<SrcDev> srcs_h;
   std::vector<TripDev> trips_h;
   std::vector<int32_t> idx_h;
+  // per front row (laid out like idx): the first column of the assembled
+  // front's lower triangle that row has a nonzero in.  Elimination fills
+  // only to the right of it (the envelope), so an update whose panel
+  // columns all lie left of every envelope start of a tile's rows (or of
+  // its columns) adds exact zeros there and is skipped.
+  std::vector<int32_t> env_h;
   const std::vector<int32_t>* maps_h = nullptr;
   Arena mem;
   FrontDev* fronts = nullptr;
@@ -451,6 +457,7 @@ struct CellStatic {
   int32_t* maps = nullptr;
   TripDev* trips = nullptr;
   int32_t* idx = nullptr;
+  int32_t* env = nullptr;
   int64_t elems = 0;
   int pmax = 0, smax = 0, ncell = 0;
   bool on_device = false;
@@ -786,13 +793,28 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
   cs->srcs_h.resize(size_t(nsrc));
   cs->trips_h.resize(size_t(ntrip));
   cs->idx_h.resize(size_t(nidx));
+  cs->env_h.resize(size_t(nidx));
   plan_parallel(nc, 16, [&](size_t ci) {
     const Cell& c = lp.cells[ci];
     const FrontDev& f = cs->fh[ci];
     for (size_t k = 0; k < c.src.size(); ++k) cs->srcs_h[size_t(f.src_begin) + k] = resolve(F, c.src[k]);
+    int32_t* env = cs->env_h.data() + f.idx;
+    for (int32_t i = 0; i < f.s; ++i) env[i] = i;
     for (size_t k = 0; k < c.trips.size(); ++k) {
       const Trip& t = c.trips[k];
       cs->trips_h[size_t(f.trip_begin) + k] = TripDev{t.i, t.j, t.ref};
+      const int32_t hi = std::max(t.i, t.j), lo = std::min(t.i, t.j);
+      env[hi] = std::min(env[hi], lo);
+    }
+    // a source block is dense: each row it reaches has a nonzero in the
+    // source's first destination column
+    for (const Source& src : c.src) {
+      const int32_t* m = lp.maps.data() + src.rowmap;
+      int32_t mn = f.s;
+      for (int32_t a = 0; a < src.dim; ++a)
+        if (m[a] >= 0) mn = std::min(mn, m[a]);
+      for (int32_t a = 0; a < src.dim; ++a)
+        if (m[a] >= 0) env[m[a]] = std::min(env[m[a]], mn);
     }
     std::copy(c.p.begin(), c.p.end(), cs->idx_h.begin() + f.idx);
     std::copy(c.q.begin(), c.q.end(), cs->idx_h.begin() + f.idx + int64_t(c.p.size()));
@@ -813,6 +835,7 @@ static void upload_cell_static(CellStatic& cs, Arena& mem, hipStream_t st) {
   cs.maps = mem.upload(*cs.maps_h, st);
   cs.trips = mem.upload(cs.trips_h, st);
   cs.idx = mem.upload(cs.idx_h, st);
+  cs.env = mem.upload(cs.env_h, st);
   upload_sweep(cs.sw, mem, st);
   cs.on_device = true;
 }
@@ -928,7 +951,8 @@ static inline int ldl_timed(int64_t nf) { return nf >= 256 ? LDL_VARIANTS : LDL_
 template <typename T>
 static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
                         int* info_d, int definite, hipStream_t st, bool bounds = false,
-                        bool sorted = false, int variant = LDL_MFMA, int* counter = nullptr) {
+                        bool sorted = false, int variant = LDL_MFMA, int* counter = nullptr,
+                        const int32_t* env = nullptr) {
   if (fh.empty()) return;
   if (variant == LDL_FRONT && counter) {
     // one persistent launch: a full round of the device, fronts from a queue
@@ -980,19 +1004,22 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     // bound, so many small work-groups per CU do better than few large ones
     hipLaunchKernelGGL(k_ldl_diag<T>, dim3(nf), dim3(kDiagThreads), 0, st, pool, fronts_d, j0,
                        info_d, definite);
+    // (rows of exact zeros are skipped only where every pivot is positive:
+    // an indefinite pivot would turn their zeros into -0)
     if (maxr > 0)
       hipLaunchKernelGGL(k_ldl_rows<T>, dim3(front_tile_grid(nf, maxr, "panel grid")),
-                         dim3(kThreads), 0, st, pool, fronts_d, j0, int(nf), int(maxr));
+                         dim3(kThreads), 0, st, pool, fronts_d, j0, int(nf), int(maxr),
+                         definite ? env : nullptr);
   };
   auto update = [&](unsigned nf, int j0, int64_t mt, int mode) {
     if (mt <= 0) return;
     const unsigned g = front_tile_grid(nf, mt, "trailing-update grid");
     if (variant == LDL_MFMA)
       hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d,
-                         j0, int(nf), int(mt), mode);
+                         j0, int(nf), int(mt), mode, env);
     else
       hipLaunchKernelGGL(k_ldl_update<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d, j0,
-                         int(nf), int(mt));
+                         int(nf), int(mt), env);
   };
   // panels in pairs (delayed update) on the matrix cores, one at a time
   // otherwise.  Pairs start at multiples of 2 kNB whatever the counts (a
@@ -1391,10 +1418,10 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
       F, tune_key(FAM_LDL, int(sizeof(T)), S.pmax, S.smax, S.ncell), LDL_VARIANTS, LDL_MFMA, D.pool,
       size_t(S.elems) * sizeof(T), st, [&](int v) {
         batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, v,
-                       ldl_counter);
+                       ldl_counter, S.env);
       }, ldl_timed(S.ncell));
   batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, var,
-                 ldl_counter);
+                 ldl_counter, S.env);
   // The apply form and its packed copy are read by the sweeps only: they run
   // on the side stream after this level's IDs, beside the host's skeleton
   // bookkeeping and the next level's planning.  They touch the first p
