@@ -2180,9 +2180,19 @@ static void run_factor(hifde_factor_s& F, hifde_tree_s* tree, hipStream_t st) {
     if (total > 0) {
       int* all = F.mem.get<int>(total);
       size_t at = 0;
-      for (const Part& q : parts) {
-        HIP_CHECK(hipMemcpyAsync(all + at, q.info, q.n * sizeof(int), hipMemcpyDeviceToDevice, st));
-        at += q.n;
+      for (size_t b = 0; b < parts.size(); b += kFlagParts) {   // one launch per table
+        FlagParts tab{};
+        int64_t mx = 0;
+        tab.off[0] = int64_t(at);
+        for (size_t i = b; i < std::min(parts.size(), b + kFlagParts); ++i) {
+          tab.p[tab.n] = parts[i].info;
+          at += parts[i].n;
+          tab.off[++tab.n] = int64_t(at);
+          mx = std::max<int64_t>(mx, int64_t(parts[i].n));
+        }
+        const unsigned bx = unsigned(std::min<int64_t>(64, (mx + kThreads - 1) / kThreads));
+        hipLaunchKernelGGL(k_gather_flags, dim3(bx, unsigned(tab.n)), dim3(kThreads), 0, st, tab,
+                           all);
       }
       int* hp = static_cast<int*>(F.host_stage(total * sizeof(int)));
       HIP_CHECK(hipMemcpyAsync(hp, all, total * sizeof(int), hipMemcpyDeviceToHost, st));
