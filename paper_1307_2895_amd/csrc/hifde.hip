@@ -939,9 +939,13 @@ static unsigned active_fronts(const std::vector<FrontDev>& fh, int j, bool sorte
 }
 
 // Trailing-update variants of the batched LDL^T.
-enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_FRONT = 2, LDL_VARIANTS = 3 };
+// LDL_MFMA takes the panels in pairs (one pass of the trailing block per
+// two panels); LDL_MFMA1 one at a time, whose narrower panels skip more
+// tiles outside the fronts' envelopes.
+enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_FRONT = 2, LDL_MFMA1 = 3, LDL_VARIANTS = 4 };
 // Variants the tuner times for a launch of nf fronts: the one-launch form
-// (one work-group per front) only when the fronts fill the device.
+// (one work-group per front) and the single-panel matrix-core form only
+// when the fronts fill the device.
 static inline int ldl_timed(int64_t nf) { return nf >= 256 ? LDL_VARIANTS : LDL_FRONT; }
 
 // With `bounds`, the p of fh are upper bounds of the device fronts' pivot
@@ -1014,7 +1018,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
   auto update = [&](unsigned nf, int j0, int64_t mt, int mode) {
     if (mt <= 0) return;
     const unsigned g = front_tile_grid(nf, mt, "trailing-update grid");
-    if (variant == LDL_MFMA)
+    if (variant == LDL_MFMA || variant == LDL_MFMA1)
       hipLaunchKernelGGL(k_ldl_update_mfma<T>, dim3(g), dim3(kThreads), 0, st, pool, fronts_d,
                          j0, int(nf), int(mt), mode, env);
     else
