@@ -85,6 +85,28 @@ def test_persistent_ldl_is_bitwise_the_panel_launches(prec, case, monkeypatch):
     assert torch.equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("prec", [0, 2])
+def test_envelope_skips_are_exact_on_indefinite_fronts(prec, monkeypatch):
+    """Indefinite (Helmholtz-type) factorization: the panel launches skip
+    trailing-update tiles outside the fronts' envelopes, the persistent
+    whole-front form does not; with negative pivots in the fronts the two
+    must still agree bit for bit (skipped tiles would have received exact
+    zeros, and stay +0)."""
+    import paper_1307_2895_amd as H
+    n, m = 64, 8
+    a = W.make_field(2, n, "const", None)
+    b = torch.full((n * n,), -(2 * np.pi * 8) ** 2, dtype=torch.float64).cuda()
+    f = torch.from_numpy(W.make_rhs(n * n, 2, 6)).cuda()
+    out = []
+    for force in ("ldl=1", "ldl=2"):
+        monkeypatch.setenv("HIFDE_TUNE_FORCE", force)
+        T = H.hifde_build_tree(2, n, m, 0)
+        F = H.hifde_factor(T, torch_inputs(a), b, 1e-6, prec, flags=H.HIFDE_INDEFINITE)
+        out.append(H.hifde_solve(F, f))
+        F.free()
+    assert torch.equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("case", [(3, 32, 4, "const", None), (3, 16, 2, "lognormal_grf", 4),
                                   (2, 256, 4, "bernoulli_contrast", 2),
                                   (2, 256, 16, "bernoulli_contrast", 2),
