@@ -450,6 +450,8 @@ struct CellStatic {
   // columns all lie left of every envelope start of a tile's rows (or of
   // its columns) adds exact zeros there and is skipped.
   std::vector<int32_t> env_h;
+  // widest band of the eliminated blocks: max over p rows i of i - env(i)
+  int pband = 0;
   const std::vector<int32_t>* maps_h = nullptr;
   Arena mem;
   FrontDev* fronts = nullptr;
@@ -794,6 +796,7 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
   cs->trips_h.resize(size_t(ntrip));
   cs->idx_h.resize(size_t(nidx));
   cs->env_h.resize(size_t(nidx));
+  std::vector<int32_t> band(nc, 0);
   plan_parallel(nc, 16, [&](size_t ci) {
     const Cell& c = lp.cells[ci];
     const FrontDev& f = cs->fh[ci];
@@ -816,10 +819,12 @@ static std::shared_ptr<CellStatic> make_cell_static(const hifde_factor_s& F, con
       for (int32_t a = 0; a < src.dim; ++a)
         if (m[a] >= 0) env[m[a]] = std::min(env[m[a]], mn);
     }
+    for (int32_t i = 0; i < f.p; ++i) band[ci] = std::max(band[ci], i - env[i]);
     std::copy(c.p.begin(), c.p.end(), cs->idx_h.begin() + f.idx);
     std::copy(c.q.begin(), c.q.end(), cs->idx_h.begin() + f.idx + int64_t(c.p.size()));
   });
   cs->elems = off;
+  for (int32_t b : band) cs->pband = std::max(cs->pband, int(b));
   cs->ncell = int(cs->fh.size());
   cs->maps_h = &lp.maps;
   build_sweep(cs->sw, cs->fh, true, &cs->idx_h, one_launch ? F.g.N : 0);
@@ -942,7 +947,9 @@ static unsigned active_fronts(const std::vector<FrontDev>& fh, int j, bool sorte
 // LDL_MFMA takes the panels in pairs (one pass of the trailing block per
 // two panels); LDL_MFMA1 one at a time, whose narrower panels skip more
 // tiles outside the fronts' envelopes.
-enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_FRONT = 2, LDL_MFMA1 = 3, LDL_VARIANTS = 4 };
+// LDL_BAND eliminates banded cells in one launch (k_ldl_band), when the
+// level's band is narrower than a panel.
+enum { LDL_FMA = 0, LDL_MFMA = 1, LDL_FRONT = 2, LDL_MFMA1 = 3, LDL_BAND = 4, LDL_VARIANTS = 5 };
 // Variants the tuner times for a launch of nf fronts: the one-launch form
 // (one work-group per front) and the single-panel matrix-core form only
 // when the fronts fill the device.
@@ -956,8 +963,33 @@ template <typename T>
 static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev* fronts_d,
                         int* info_d, int definite, hipStream_t st, bool bounds = false,
                         bool sorted = false, int variant = LDL_MFMA, int* counter = nullptr,
-                        const int32_t* env = nullptr) {
+                        const int32_t* env = nullptr, int band = -1) {
   if (fh.empty()) return;
+  if (variant == LDL_BAND) {
+    int pm = 0;
+    for (const auto& f : fh) pm = std::max(pm, f.p);
+    const int bwt = band < 8 ? 8 : band < 16 ? 16 : band < 17 ? 17 : 32;
+    const size_t smem =
+        (size_t(std::max(pm * bwt, 2 * kTB * (kNB + 1))) + size_t(pm)) * sizeof(T);
+    if (!bounds && band >= 0 && band < kNB && smem <= 64 * 1024) {
+      const dim3 g(unsigned(fh.size()));
+      if (band < 8)
+        hipLaunchKernelGGL((k_ldl_band<T, 8>), g, dim3(kThreads), smem, st, pool, fronts_d,
+                           info_d, definite, band);
+      else if (band < 16)
+        hipLaunchKernelGGL((k_ldl_band<T, 16>), g, dim3(kThreads), smem, st, pool, fronts_d,
+                           info_d, definite, band);
+      else if (band < 17)
+        hipLaunchKernelGGL((k_ldl_band<T, 17>), g, dim3(kThreads), smem, st, pool, fronts_d,
+                           info_d, definite, band);
+      else
+        hipLaunchKernelGGL((k_ldl_band<T, 32>), g, dim3(kThreads), smem, st, pool, fronts_d,
+                           info_d, definite, band);
+      HIP_CHECK(hipGetLastError());
+      return;
+    }
+    variant = LDL_MFMA;
+  }
   if (variant == LDL_FRONT && counter) {
     // one persistent launch: a full round of the device, fronts from a queue
     static const std::pair<int, int> occ = [] {
@@ -1422,10 +1454,10 @@ static void cells_level(hifde_factor_s& F, hifde_tree_s* tree, int l, hipStream_
       F, tune_key(FAM_LDL, int(sizeof(T)), S.pmax, S.smax, S.ncell), LDL_VARIANTS, LDL_MFMA, D.pool,
       size_t(S.elems) * sizeof(T), st, [&](int v) {
         batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, v,
-                       ldl_counter, S.env);
+                       ldl_counter, S.env, S.pband);
       }, ldl_timed(S.ncell));
   batched_ldl<T>(static_cast<T*>(D.pool), fs, fs_d, D.info, F.definite, st, false, true, var,
-                 ldl_counter, S.env);
+                 ldl_counter, S.env, S.pband);
   // The apply form and its packed copy are read by the sweeps only: they run
   // on the side stream after this level's IDs, beside the host's skeleton
   // bookkeeping and the next level's planning.  They touch the first p

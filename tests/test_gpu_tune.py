@@ -24,7 +24,7 @@ torch = pytest.importorskip("torch")
                                    "ldl=0,cpqr=1,inv=1", "ldl=1,cpqr=0,inv=0",
                                    "ldl=1,cpqr=2,inv=1", "ldl=1,cpqr=3,inv=1",
                                    "ldl=2,cpqr=0,inv=1", "ldl=1,cpqr=0,inv=2",
-                                   "ldl=3,cpqr=1,inv=1"])
+                                   "ldl=3,cpqr=1,inv=1", "ldl=4,cpqr=0,inv=1"])
 @pytest.mark.parametrize("case", [(2, 64, 8, 1e-6, "bernoulli_contrast", 2),
                                   (3, 16, 2, 1e-3, "lognormal_grf", 4)])
 def test_every_variant_matches_oracle(force, case, monkeypatch):
