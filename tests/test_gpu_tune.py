@@ -107,6 +107,54 @@ def test_envelope_skips_are_exact_on_indefinite_fronts(prec, monkeypatch):
     assert torch.equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("case", [(2, 64, 16, "bernoulli_contrast", 2),   # band 15 and 16
+                                  (2, 60, 8, "loguniform", 3)])          # ragged, band 7
+def test_banded_elimination_mixed_converges(prec, case, monkeypatch):
+    """The banded elimination forced in the mixed precisions (float cells,
+    and double cells rounded to float): PCG reaches 1e-12 and the solution
+    of the oracle's FP64 factorization's PCG."""
+    import paper_1307_2895_amd as H
+    from oracle import hifde as OH
+    from oracle import pcg as OP
+    dim, n, m, field, seed = case
+    print(f"case band mixed {case} prec={prec}", flush=True)
+    monkeypatch.setenv("HIFDE_TUNE_FORCE", "ldl=4")
+    a = W.make_field(dim, n, field, seed)
+    OF = oracle_factor(dim, n, m, a, 1e-6)
+    f = W.make_rhs(n ** dim, 2, 9)
+    uo, _, _ = OP.pcg_multi(OF.A, f, lambda r: OH.solve(OF, r), 1e-12, 100)
+    T = H.hifde_build_tree(dim, n, m, 0)
+    F = H.hifde_factor(T, torch_inputs(a), None, 1e-6, prec)
+    u, its, rel = H.hifde_pcg(F, torch.from_numpy(f).cuda(), tol=1e-12, maxit=100)
+    u = u.cpu().numpy()
+    print("iterations", its, "relres", rel)
+    assert np.all(rel <= 1.5e-12)
+    err = np.linalg.norm(OF.A @ (u - uo), axis=0) / np.linalg.norm(f, axis=0)
+    assert np.all(err <= 1e-10), err
+    F.free()
+
+
+def test_banded_elimination_indefinite(monkeypatch):
+    """The banded elimination on indefinite cells (negative pivots, FP64)
+    agrees with the panel launches to rounding in F^-1 f."""
+    import paper_1307_2895_amd as H
+    n, m = 64, 16
+    a = W.make_field(2, n, "const", None)
+    b = torch.full((n * n,), -(2 * np.pi * 8) ** 2, dtype=torch.float64).cuda()
+    f = torch.from_numpy(W.make_rhs(n * n, 2, 7)).cuda()
+    out = []
+    for force in ("ldl=1", "ldl=4"):
+        monkeypatch.setenv("HIFDE_TUNE_FORCE", force)
+        T = H.hifde_build_tree(2, n, m, 0)
+        F = H.hifde_factor(T, torch_inputs(a), b, 1e-6, 0, flags=H.HIFDE_INDEFINITE)
+        out.append(H.hifde_solve(F, f).cpu().numpy())
+        F.free()
+    d = np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[0])
+    print("F^-1 f difference", d)
+    assert d <= 1e-9
+
+
 @pytest.mark.parametrize("case", [(3, 32, 4, "const", None), (3, 16, 2, "lognormal_grf", 4),
                                   (2, 256, 4, "bernoulli_contrast", 2),
                                   (2, 256, 16, "bernoulli_contrast", 2),
