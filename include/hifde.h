@@ -100,7 +100,8 @@ enum {
                                    |c^N| Gaussian matrix drawn from
                                    Philox4x32-10 (key 0x9E3779B97F4A7C15,
                                    counter (row, column, group key, level),
-                                   Box-Muller); same rank rule.  Fewer rows
+                                   Box-Muller in the working type); same
+                                   rank rule.  Fewer rows
                                    for the pivoted QR, plus one product on
                                    the matrix cores                        */
   HIFDE_RETRY_FP64 = 1024u      /* a float factorization (HIFDE_MIXED or
