@@ -970,7 +970,7 @@ static void batched_ldl(T* pool, const std::vector<FrontDev>& fh, const FrontDev
     for (const auto& f : fh) pm = std::max(pm, f.p);
     const int bwt = band < 8 ? 8 : band < 16 ? 16 : band < 17 ? 17 : 32;
     const size_t smem = (size_t(bwt * bwt) +
-                         size_t(std::max((pm + bwt) * bwt, 2 * kTB * (kNB + 1))) + size_t(pm)) *
+                         size_t(std::max((pm + bwt) * bwt, 2 * kTB * (kNB + 1))) + size_t(2 * pm)) *
                         sizeof(T);
     if (!bounds && band >= 0 && band < kNB && smem <= 64 * 1024) {
       const dim3 g(unsigned(fh.size()));
